@@ -1,0 +1,341 @@
+"""Plain FP64 CPU oracle of the ISDF decomposition (weighted K-means + fit + adjoint).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module; the product library
+never does, and this file shares no code, table or helper with the HIP path.
+
+Written from arXiv:2208.07731 (Jiao et al., "Complex-valued K-means
+clustering of interpolative separable density fitting ...").  Every function
+cites the passage it follows.  Arithmetic is numpy/scipy complex128/float64,
+one library primitive per step (matmul, Cholesky, triangular solve), with no
+blocking or fusion beyond what the cited definition states.
+
+Readings taken where the paper is silent or garbled (each is also listed in
+the design notes):
+* Z has entries phi_i(r) conj(psi_j(r)) (Sec. 2.1, eq. decomposition / Cmu);
+  the least-squares solution of Z ~ Theta C for complex data is
+  Theta = Z C^H (C C^H)^-1 (eq. theta written with transposes in real
+  notation), and the (r, nu) entry of Z C^H is
+  P^phi(r, r_nu) * conj(P^psi(r, r_nu)) (eq. muRownuCol / muRownuColden).
+* C C^H is the Hermitian positive definite block of Z C^H at the
+  interpolation rows (Sec. 2.4); it is factored by Cholesky.  A non positive
+  definite block is reported, never regularised.
+* K-means (Alg. 1, eqs. opt / r_k): Euclidean distance on grid coordinates
+  (no minimum image), lowest centroid index wins ties, a cluster with zero
+  total weight keeps its centroid, at most `max_iter` classify+update rounds
+  that stop early at a fixed point, then one final classification; the
+  interpolation point of a cluster is its member nearest to the final
+  centroid (lowest grid index on ties), because interpolation points are grid
+  points (Sec. 2.1) while centroids are not.
+* Distances: D = ((s0*dx*dx) + (s1*dy*dy)) + (s2*dz*dz) in grid units with
+  s_a = (h_a / min h)^2 (s = 1 on cubic grids, where integer-valued
+  coordinates make first-iteration ties exact).
+* The adjoint is not in the paper; it is derived by reverse-mode
+  differentiation of the fit with the interpolation points held fixed, in
+  PyTorch's complex-gradient convention dL/dRe + i dL/dIm.
+
+Parity status: every function here is pinned by the CPU tests against
+closed forms, brute force or library least squares, except where a
+docstring says "parity unpinned".
+"""
+from __future__ import annotations
+
+import concurrent.futures as _cf
+import os
+
+import numpy as np
+import scipy.linalg as sla
+
+__all__ = [
+    "WEIGHT_KINDS", "weight", "grid_points", "metric_scale", "sqdist",
+    "assign", "update", "snap", "kmeans", "gather", "gram_blocks", "hadamard",
+    "fit", "fit_theta", "fit_backward", "fit_residual", "cc_condition",
+    "explicit_z",
+]
+
+# --------------------------------------------------------------------------
+# a1: weight function (Sec. 2.2, eq. weight function and eq. weight function 2)
+# --------------------------------------------------------------------------
+WEIGHT_KINDS = ("ssm", "psm", "sm", "scm", "sqm")
+
+
+def _abs_pow(x: np.ndarray, alpha: int) -> np.ndarray:
+    """|x|^alpha elementwise for complex x, from s = re^2 + im^2."""
+    s = x.real * x.real + x.imag * x.imag
+    if alpha == 2:
+        return s
+    if alpha == 1:
+        return np.sqrt(s)
+    if alpha == 3:
+        return s * np.sqrt(s)
+    if alpha == 4:
+        return s * s
+    raise ValueError(alpha)
+
+
+def weight(phi: np.ndarray, psi: np.ndarray | None = None, kind: str = "ssm") -> np.ndarray:
+    """K-means weight w(r), float64 (N_r,).
+
+    * "ssm" (the paper's improved weight, alpha = 2 in eq. weight function 2):
+      sum_i |phi_i|^2 + sum_j |psi_j|^2;
+    * "sm", "scm", "sqm": the same sum with alpha = 1, 3, 4 (Sec. 2.2);
+    * "psm" (the earlier real-valued weight, eq. weight function):
+      (sum_i |phi_i|^2) * (sum_j |psi_j|^2).
+    psi=None means Psi is Phi.
+    """
+    if psi is None:
+        psi = phi
+    if kind == "psm":
+        return _abs_pow(phi, 2).sum(axis=1) * _abs_pow(psi, 2).sum(axis=1)
+    alpha = {"ssm": 2, "sm": 1, "scm": 3, "sqm": 4}[kind]
+    return _abs_pow(phi, alpha).sum(axis=1) + _abs_pow(psi, alpha).sum(axis=1)
+
+
+# --------------------------------------------------------------------------
+# a2-a6: weighted K-means on grid points (Sec. 2.2, eqs. opt, r_k; Alg. 1)
+# --------------------------------------------------------------------------
+def grid_points(n) -> np.ndarray:
+    """Grid coordinates in grid units, float64 (N_r, 3); p = (i*n1 + j)*n2 + k."""
+    n0, n1, n2 = (n, n, n) if np.isscalar(n) else tuple(n)
+    i, j, k = np.meshgrid(np.arange(n0), np.arange(n1), np.arange(n2), indexing="ij")
+    return np.stack([i.reshape(-1), j.reshape(-1), k.reshape(-1)], axis=1).astype(np.float64)
+
+
+def metric_scale(h=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """Per-axis weights s_a = (h_a / min h)^2 of the Euclidean metric."""
+    h = np.asarray(h, dtype=np.float64)
+    return (h / h.min()) ** 2
+
+
+def sqdist(pts: np.ndarray, cents: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Squared Euclidean distances (P, K): ((s0*dx*dx) + (s1*dy*dy)) + (s2*dz*dz)."""
+    dx = pts[:, None, 0] - cents[None, :, 0]
+    dy = pts[:, None, 1] - cents[None, :, 1]
+    dz = pts[:, None, 2] - cents[None, :, 2]
+    if np.all(s == 1.0):
+        return (dx * dx + dy * dy) + dz * dz
+    return (s[0] * (dx * dx) + s[1] * (dy * dy)) + s[2] * (dz * dz)
+
+
+def _threads() -> int:
+    return int(os.environ.get("ISDF_ORACLE_THREADS", os.cpu_count() or 1))
+
+
+def assign(pts: np.ndarray, cents: np.ndarray, s: np.ndarray, chunk: int = 2048):
+    """Classification step of Alg. 1 / eq. C_k: label_p = first argmin_mu D_pmu.
+
+    Returns (labels int32, d1 = nearest distance, d2 = second nearest, inf if
+    there is one centroid).
+    """
+    n_pts = pts.shape[0]
+    labels = np.empty(n_pts, dtype=np.int32)
+    d1 = np.empty(n_pts)
+    d2 = np.empty(n_pts)
+
+    def work(lo):
+        hi = min(lo + chunk, n_pts)
+        D = sqdist(pts[lo:hi], cents, s)
+        a = np.argmin(D, axis=1)
+        rows = np.arange(hi - lo)
+        labels[lo:hi] = a
+        d1[lo:hi] = D[rows, a]
+        if D.shape[1] > 1:
+            D[rows, a] = np.inf
+            d2[lo:hi] = D.min(axis=1)
+        else:
+            d2[lo:hi] = np.inf
+
+    starts = range(0, n_pts, chunk)
+    nt = _threads()
+    if nt > 1 and n_pts > chunk:
+        with _cf.ThreadPoolExecutor(nt) as ex:
+            list(ex.map(work, starts))
+    else:
+        for lo in starts:
+            work(lo)
+    return labels, d1, d2
+
+
+def update(pts: np.ndarray, w: np.ndarray, labels: np.ndarray, cents: np.ndarray):
+    """Centroid step of Alg. 1 / eq. r_k: r_mu = sum_{C_mu} w r / sum_{C_mu} w.
+
+    A cluster whose total weight is zero keeps its centroid.  Returns
+    (new centroids, number of such clusters).
+    """
+    K = cents.shape[0]
+    sw = np.bincount(labels, weights=w, minlength=K)
+    out = cents.copy()
+    ok = sw > 0
+    for a in range(3):
+        sa = np.bincount(labels, weights=w * pts[:, a], minlength=K)
+        out[ok, a] = sa[ok] / sw[ok]
+    return out, int(K - ok.sum())
+
+
+def snap(pts: np.ndarray, labels: np.ndarray, cents: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Interpolation point of each cluster: its member nearest to the centroid,
+    lowest grid index on ties; -1 for an empty cluster (Sec. 2.1: interpolation
+    points are grid points; Alg. 1's last step read as this snap)."""
+    K = cents.shape[0]
+    c = cents[labels]
+    dx = pts[:, 0] - c[:, 0]
+    dy = pts[:, 1] - c[:, 1]
+    dz = pts[:, 2] - c[:, 2]
+    if np.all(s == 1.0):
+        d = (dx * dx + dy * dy) + dz * dz
+    else:
+        d = (s[0] * (dx * dx) + s[1] * (dy * dy)) + s[2] * (dz * dz)
+    p = np.arange(pts.shape[0])
+    order = np.lexsort((p, d, labels))
+    lab_sorted = labels[order]
+    first = np.ones(order.shape[0], dtype=bool)
+    first[1:] = lab_sorted[1:] != lab_sorted[:-1]
+    idx = np.full(K, -1, dtype=np.int32)
+    idx[lab_sorted[first]] = order[first]
+    return idx
+
+
+def kmeans(n, w: np.ndarray, c0: np.ndarray, max_iter: int, h=(1.0, 1.0, 1.0),
+           near_tie_rel: float = 1e-6) -> dict:
+    """Weighted K-means on the grid (Alg. 1) with the readings in the module
+    docstring.  Returns dict with idx, centroids, labels, d1, d2, J (objective
+    of eq. opt at each classification), iters (update rounds run), converged,
+    empty (clusters with zero weight at the last update), ties, near_ties,
+    near_tie_mask."""
+    pts = grid_points(n)
+    s = metric_scale(h)
+    c = np.array(c0, dtype=np.float64, copy=True)
+    prev = None
+    J = []
+    iters = 0
+    converged = False
+    empty = 0
+    labels = d1 = d2 = None
+    for _ in range(max_iter):
+        labels, d1, d2 = assign(pts, c, s)
+        J.append(float(np.dot(w, d1)))
+        if prev is not None and np.array_equal(labels, prev):
+            converged = True
+            break
+        c, empty = update(pts, w, labels, c)
+        iters += 1
+        prev = labels
+    if not converged:
+        labels, d1, d2 = assign(pts, c, s)
+        J.append(float(np.dot(w, d1)))
+    idx = snap(pts, labels, c, s)
+    gap = d2 - d1
+    near = gap <= near_tie_rel * d2
+    return dict(idx=idx, centroids=c, labels=labels, d1=d1, d2=d2, J=np.array(J),
+                iters=iters, converged=converged, empty=empty,
+                ties=int(np.count_nonzero(d1 == d2)), near_ties=int(near.sum()),
+                near_tie_mask=near)
+
+
+# --------------------------------------------------------------------------
+# a7-a12: least-squares fit of the interpolation vectors (Sec. 2.1,
+# eqs. decomMatrix, theta, muRownuCol, muRownuColden; Sec. 2.4)
+# --------------------------------------------------------------------------
+def gather(x: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """Rows of an orbital matrix at the interpolation points (eq. Cmu)."""
+    return x[np.asarray(idx)]
+
+
+def gram_blocks(phi: np.ndarray, psi: np.ndarray, idx: np.ndarray, rows=None):
+    """A = Phi Phi_mu^H and B = Psi Psi_mu^H, i.e. P^phi(r, r_nu) and
+    P^psi(r, r_nu) of eq. muRownuColden, for all grid rows (or `rows`)."""
+    pr = phi if rows is None else phi[rows]
+    sr = psi if rows is None else psi[rows]
+    A = pr @ gather(phi, idx).conj().T
+    B = sr @ gather(psi, idx).conj().T
+    return A, B
+
+
+def hadamard(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """(Z C^H)(r, nu) = P^phi(r, r_nu) conj(P^psi(r, r_nu)) (eq. muRownuCol, with
+    the conjugate that complex orbitals require)."""
+    return A * B.conj()
+
+
+def _cc(phi, psi, idx):
+    """C C^H: the rows of Z C^H at the interpolation points (Sec. 2.4)."""
+    Am, Bm = gram_blocks(phi, psi, idx, rows=np.asarray(idx))
+    return hadamard(Am, Bm)
+
+
+def fit(phi: np.ndarray, psi: np.ndarray, idx: np.ndarray, rows=None) -> dict:
+    """Theta = Z C^H (C C^H)^-1 (eq. theta), by Cholesky of C C^H and two
+    triangular solves.  Returns dict(theta, G, M, L, A, B) for all rows (or
+    the rows listed in `rows`: rows of Theta are independent given C C^H)."""
+    A, B = gram_blocks(phi, psi, idx, rows)
+    G = hadamard(A, B)
+    M = _cc(phi, psi, idx)
+    try:
+        L = sla.cholesky(M, lower=True, check_finite=True)
+    except np.linalg.LinAlgError as e:
+        raise np.linalg.LinAlgError("C C^H is not positive definite") from e
+    Y = sla.solve_triangular(L, G.conj().T, lower=True)
+    theta_h = sla.solve_triangular(L.conj().T, Y, lower=False)
+    return dict(theta=theta_h.conj().T, G=G, M=M, L=L, A=A, B=B)
+
+
+def fit_theta(phi, psi, idx, rows=None) -> np.ndarray:
+    return fit(phi, psi, idx, rows)["theta"]
+
+
+def cc_condition(phi, psi, idx) -> float:
+    """2-norm condition number of C C^H (diagnostic)."""
+    ev = np.linalg.eigvalsh(_cc(phi, psi, idx))
+    return float(ev[-1] / ev[0]) if ev[0] > 0 else float("inf")
+
+
+def fit_residual(phi, psi, idx, theta=None) -> float:
+    """||Z - Theta C||_F^2 without forming Z:
+    sum_r rho_phi(r) rho_psi(r) - Re sum conj(Z C^H) . Theta, valid for the
+    least-squares Theta (diagnostic; the quantity Appendix A bounds)."""
+    f = fit(phi, psi, idx)
+    th = f["theta"] if theta is None else theta
+    rp = (phi.real ** 2 + phi.imag ** 2).sum(axis=1)
+    rs = (psi.real ** 2 + psi.imag ** 2).sum(axis=1)
+    return float(np.dot(rp, rs) - np.real(np.sum(f["G"].conj() * th)))
+
+
+def explicit_z(phi: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """Z (N_r x N_phi N_psi), z_(i,j)(r) = phi_i(r) conj(psi_j(r)) (Sec. 2.1).
+    Tiny inputs only: memory is O(N_r N_phi N_psi)."""
+    return (phi[:, :, None] * psi.conj()[:, None, :]).reshape(phi.shape[0], -1)
+
+
+# --------------------------------------------------------------------------
+# a13-a16: adjoint of the fit with the interpolation points fixed (derived)
+# --------------------------------------------------------------------------
+def fit_backward(phi: np.ndarray, psi: np.ndarray, idx: np.ndarray,
+                 theta_bar: np.ndarray | None = None, g: np.ndarray | None = None) -> dict:
+    """Gradients of a real loss through Theta = G M^-1, G = A . conj(B),
+    M = G[idx], A = Phi Phi_mu^H, B = Psi Psi_mu^H.
+
+    theta_bar given: the upstream gradient dL/dRe(Theta) + i dL/dIm(Theta).
+    theta_bar None: fused loss L = sum_r g_r sum_mu |Theta_rmu|^2, for which
+    theta_bar = 2 g . Theta.
+    Returns dict(dphi, dpsi, loss).  The two orbital sets are treated as
+    independent inputs even when they hold equal values.
+    """
+    idx = np.asarray(idx)
+    f = fit(phi, psi, idx)
+    th, A, B, L = f["theta"], f["A"], f["B"], f["L"]
+    loss = None
+    if theta_bar is None:
+        loss = float(np.sum(g[:, None] * (th.real ** 2 + th.imag ** 2)))
+        theta_bar = 2.0 * g[:, None] * th
+    # S = theta_bar M^-1  (M Hermitian): S^H = M^-1 theta_bar^H
+    S = sla.cho_solve((L, True), theta_bar.conj().T).conj().T
+    Mbar = -(th.conj().T @ S)
+    Gbar = S.copy()
+    Gbar[idx] += Mbar
+    Abar = Gbar * B
+    Bbar = Gbar.conj() * A
+    dphi = Abar @ gather(phi, idx)
+    dphi[idx] += Abar.conj().T @ phi
+    dpsi = Bbar @ gather(psi, idx)
+    dpsi[idx] += Bbar.conj().T @ psi
+    return dict(dphi=dphi, dpsi=dpsi, loss=loss)
