@@ -1,0 +1,226 @@
+/*
+ * isdf.h -- C ABI of the MI355X (gfx950) ISDF library (libisdf.so).
+ *
+ * Interpolative separable density fitting of complex Kohn-Sham orbitals,
+ * after Jiao et al., arXiv:2208.07731:
+ *   Z(r, (i,j)) = phi_i(r) conj(psi_j(r))          (Sec. 2.1)
+ *   Z ~ Theta C,  C = rows of Z at N_mu interpolation points r_mu
+ *   Theta = Z C^H (C C^H)^-1                        (eq. theta)
+ * with Z C^H = (Phi Phi_mu^H) .* conj(Psi Psi_mu^H) (eqs. muRownuCol,
+ * muRownuColden), so Z is never formed.  The interpolation points come from
+ * weighted K-means over the grid points (Sec. 2.2, Alg. 1) with the
+ * sum-of-square-moduli weight (eq. weight function 2, alpha = 2).
+ *
+ * Conventions shared by every call:
+ *  - Every pointer is DEVICE memory unless marked (host).  The caller owns
+ *    all memory; the library allocates nothing and keeps no state between
+ *    calls.
+ *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = default
+ *    stream).  The return value reports argument errors found on the host
+ *    before anything is enqueued (negative codes; nothing is written).
+ *    Conditions found by the GPU are written to the device-side `info`
+ *    struct, valid once the caller has synchronised `stream`.
+ *  - Orbital matrices are r-major: row p of Phi holds phi_1(r_p) ..
+ *    phi_{n_phi}(r_p) as interleaved complex numbers (re, im), row p starts
+ *    at element p * ld (ld >= n in complex elements).  ISDF_C128 = pairs of
+ *    double, ISDF_C64 = pairs of float.
+ *  - Grid point p = (i * n[1] + j) * n[2] + k sits at grid coordinates
+ *    (i, j, k); spacings h[3] weigh the Euclidean metric per axis by
+ *    (h_a / min h)^2 (cubic grids: plain grid units).
+ *  - psi == phi (same pointer, ld and count) selects the aliased path:
+ *    Theta is real (the fit of |phi|^2-type products) and is stored as real
+ *    numbers; otherwise Theta is complex.
+ *  - Calls that share a workspace or output buffer must not overlap.
+ */
+#ifndef ISDF_H
+#define ISDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+typedef enum {
+  ISDF_OK = 0,
+  ISDF_E_ARG = -1,          /* invalid argument (host check, nothing enqueued) */
+  ISDF_E_WORKSPACE = -2,    /* ws_bytes below the *_workspace query */
+  ISDF_E_HIP = -3,          /* a HIP runtime call failed while enqueueing */
+  ISDF_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  ISDF_E_NOT_PD = 1,        /* device: C C^H not positive definite (see info->pivot) */
+  ISDF_E_NONFINITE = 2,     /* device: NaN or Inf in the orbitals / weight */
+  ISDF_W_EMPTY_CLUSTER = 3, /* device: a cluster lost all members (idx = -1) */
+  ISDF_E_BAD_IDX = 4        /* device: interpolation index out of range or repeated */
+} isdf_status;
+
+typedef enum { ISDF_C128 = 0, ISDF_C64 = 1 } isdf_dtype;
+
+/* Precision of the Gram contractions Phi Phi_mu^H, Psi Psi_mu^H (and of the
+ * adjoint contractions with the orbitals).  The factorisation and inverse
+ * of C C^H and the product with it are always FP64. */
+typedef enum {
+  ISDF_P_FP64 = 0,    /* FP64 MFMA */
+  ISDF_P_FP32 = 1,    /* FP32 MFMA, FP32 accumulation */
+  ISDF_P_BF16X6 = 2,  /* operands split in three BF16 parts, 6 products, FP32 acc */
+  ISDF_P_FP16X3 = 3   /* operands split in two scaled FP16 parts, 3 products, FP32 acc */
+} isdf_prec;
+
+/* K-means weight w(r) (Sec. 2.2).  SSM is the paper's choice. */
+typedef enum {
+  ISDF_W_SSM = 0,  /* sum_i |phi_i|^2 + sum_j |psi_j|^2   (eq. weight function 2, alpha=2) */
+  ISDF_W_PSM = 1,  /* (sum_i |phi_i|^2)(sum_j |psi_j|^2)  (eq. weight function)           */
+  ISDF_W_SM = 2,   /* alpha = 1 */
+  ISDF_W_SCM = 3,  /* alpha = 3 */
+  ISDF_W_SQM = 4   /* alpha = 4 */
+} isdf_weight;
+
+typedef struct {
+  int32_t n[3];  /* grid points per axis, N_r = n0 n1 n2 */
+  double h[3];   /* spacings (any positive unit); only their ratios matter */
+} isdf_grid;
+
+/* -------------------------------------------------------------- K-means */
+/* flags of isdf_kmeans */
+#define ISDF_KM_WEIGHT_GIVEN 1u /* `w` holds the weight on entry: skip its evaluation */
+
+/* Written by the device at the end of isdf_kmeans. */
+typedef struct {
+  int32_t status;       /* ISDF_OK, ISDF_W_EMPTY_CLUSTER or ISDF_E_NONFINITE */
+  int32_t iters;        /* classify+update rounds applied */
+  int32_t converged;    /* 1 if a round left every label unchanged */
+  int32_t empty_update; /* clusters of zero total weight at the last update (kept) */
+  int32_t empty_final;  /* clusters without member at the final classification */
+  int32_t ties;         /* points with two exactly equidistant nearest centroids */
+  int32_t near_ties;    /* points with (d2 - d1) <= near_tie_rel * d2 */
+  int32_t changed;      /* labels changed by the last round that ran */
+  double objective;     /* sum_p w_p |r_p - c_label(p)|^2 at the final classification */
+} isdf_kmeans_info;
+
+/* Bytes of workspace isdf_kmeans needs.  Host-only, never synchronises. */
+size_t isdf_kmeans_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t max_iter);
+
+/*
+ * Weighted K-means over the grid points (Alg. 1 of the paper):
+ *   w    = weight of `weight_kind` from Phi and Psi   (skipped with ISDF_KM_WEIGHT_GIVEN)
+ *   c    = c0
+ *   repeat up to max_iter times:
+ *     label_p = argmin_mu |r_p - c_mu|^2  (Euclidean; lowest mu on ties)     (eq. C_k)
+ *     stop if no label changed since the previous round
+ *     c_mu = sum_{p in C_mu} w_p r_p / sum_{p in C_mu} w_p  (kept if the sum is 0) (eq. r_k)
+ *   final classification with the last centroids, then
+ *   idx[mu] = member of C_mu nearest to c_mu (lowest p on ties; -1 if empty).
+ * Stopping at a fixed point gives the same result as running all rounds.
+ * Arguments:
+ *   phi, psi       orbitals (see conventions); psi may equal phi.  Unused
+ *                  (may be NULL) when ISDF_KM_WEIGHT_GIVEN is set.
+ *   n_mu           number of clusters / interpolation points, 1 <= n_mu <= N_r
+ *   c0             [n_mu][3] FP64 initial centroids in grid units (read only)
+ *   max_iter       >= 0 rounds
+ *   near_tie_rel   relative gap below which a point counts as a near tie (e.g. 1e-6)
+ *   idx            [n_mu] int32 out: grid index of each interpolation point
+ *   centroids      [n_mu][3] FP64 out, final centroids (NULL: not returned)
+ *   labels         [N_r] int32 out, final cluster of every point (NULL: not returned)
+ *   w              [N_r] FP64: out (or in with ISDF_KM_WEIGHT_GIVEN); NULL: not returned
+ *   objective      [max_iter + 1] FP64 out, objective after each classification,
+ *                  unused entries -1 (NULL: not returned)
+ *   info           device struct, written at the end
+ * Deterministic: equal inputs give bitwise equal outputs.
+ */
+int isdf_kmeans(const isdf_grid* grid /* host */, isdf_dtype dt,
+                const void* phi, int64_t ld_phi, int32_t n_phi,
+                const void* psi, int64_t ld_psi, int32_t n_psi,
+                int32_t weight_kind, uint32_t flags, int32_t n_mu,
+                const double* c0, int32_t max_iter, double near_tie_rel,
+                int32_t* idx, double* centroids, int32_t* labels, double* w,
+                double* objective, isdf_kmeans_info* info,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ fit */
+/* flags of isdf_fit / isdf_fit_backward */
+#define ISDF_FIT_FACTOR 1u /* (re)build minv = (C C^H)^-1 from Phi, Psi, idx */
+
+typedef struct {
+  int32_t status;   /* ISDF_OK, ISDF_E_NOT_PD, ISDF_E_BAD_IDX */
+  int32_t pivot;    /* first non-positive Cholesky pivot (row of minv), else -1 */
+  int32_t bad_idx;  /* position in idx of the first invalid entry, else -1 */
+  int32_t reserved;
+  double pivot_min; /* min and max of the squared Cholesky diagonal of C C^H */
+  double pivot_max;
+  double loss;      /* isdf_fit_backward with the fused loss: its value */
+} isdf_fit_info;
+
+/* Elements (doubles) of the minv buffer: n'^2 with n' = n_mu (aliased) or 2 n_mu. */
+size_t isdf_fit_minv_elems(int32_t n_mu, int32_t aliased);
+
+/* Bytes of workspace for isdf_fit / isdf_fit_backward processing at most
+ * `rblock` grid rows at a time.  Host-only. */
+size_t isdf_fit_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi,
+                          int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock);
+size_t isdf_fit_backward_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi,
+                                   int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock);
+
+/*
+ * Interpolation vectors for grid rows [row0, row0 + nrows):
+ *   Theta = (Z C^H)(C C^H)^-1 (eq. theta), Z C^H = A .* conj(B),
+ *   A = Phi Phi_mu^H, B = Psi Psi_mu^H (eq. muRownuColden), C C^H = rows idx of Z C^H.
+ * Arguments:
+ *   idx      [n_mu] int32 distinct grid indices (e.g. from isdf_kmeans)
+ *   prec     precision of the Gram contractions (C C^H uses the same one)
+ *   minv     [n'][n'] FP64 (n' = n_mu aliased, else 2 n_mu): with ISDF_FIT_FACTOR
+ *            it is overwritten by (C C^H)^-1 (complex case: the real 2x2-block
+ *            form [[re, im], [-im, re]] of each entry); without the flag it
+ *            is read as left by an earlier call with the same inputs.
+ *   theta    [nrows][ld_theta] out: real (aliased) or interleaved complex,
+ *            double for ISDF_C128, float for ISDF_C64; ld_theta >= n_mu.
+ *   rblock   rows processed per internal step (bounded by the workspace query)
+ * Rows of Theta are independent given minv: any partition of the grid
+ * rows into calls gives the same values.
+ */
+int isdf_fit(const isdf_grid* grid /* host */, isdf_dtype dt,
+             const void* phi, int64_t ld_phi, int32_t n_phi,
+             const void* psi, int64_t ld_psi, int32_t n_psi,
+             const int32_t* idx, int32_t n_mu, isdf_prec prec,
+             double* minv, uint32_t flags, int64_t row0, int64_t nrows,
+             void* theta, int64_t ld_theta, int64_t rblock,
+             isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of isdf_fit with the interpolation points fixed (the paper gives
+ * no adjoint; this is reverse-mode differentiation of eq. theta).  With
+ * Theta = G M^-1, G = A .* conj(B), M = G[idx]:
+ *   S = Thetabar M^-1,  Mbar = -Theta^H S,  Gbar = S, Gbar[idx] += Mbar,
+ *   Abar = Gbar .* B,   Bbar = conj(Gbar) .* A,
+ *   dPhi = Abar Phi_mu,  dPhi[idx] += Abar^H Phi,
+ *   dPsi = Bbar Psi_mu,  dPsi[idx] += Bbar^H Psi,
+ * in PyTorch's complex-gradient convention (dL/dRe + i dL/dIm).
+ * Arguments:
+ *   minv       as left by isdf_fit with ISDF_FIT_FACTOR on the same inputs
+ *   theta_bar  [N_r][ld_tbar] upstream gradient, layout and type of Theta;
+ *              NULL selects the fused loss L = sum_r g_r sum_mu |Theta_r,mu|^2
+ *   g          [N_r] FP64 loss field (used only when theta_bar is NULL)
+ *   dphi, dpsi [N_r][ld] gradients, same type as the orbitals, overwritten;
+ *              in the aliased case dpsi may equal dphi (written once).
+ *   loss       FP64 device scalar (fused loss only; NULL: not returned)
+ *   rblock     grid rows per internal step; Theta is recomputed per block,
+ *              never stored whole
+ */
+int isdf_fit_backward(const isdf_grid* grid /* host */, isdf_dtype dt,
+                      const void* phi, int64_t ld_phi, int32_t n_phi,
+                      const void* psi, int64_t ld_psi, int32_t n_psi,
+                      const int32_t* idx, int32_t n_mu, isdf_prec prec,
+                      const double* minv,
+                      const void* theta_bar, int64_t ld_tbar, const double* g,
+                      void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi,
+                      double* loss, int64_t rblock,
+                      isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- misc */
+const char* isdf_version(void);
+const char* isdf_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISDF_H */

@@ -225,7 +225,7 @@ def kmeans(n, w: np.ndarray, c0: np.ndarray, max_iter: int, h=(1.0, 1.0, 1.0),
         J.append(float(np.dot(w, d1)))
     idx = snap(pts, labels, c, s)
     gap = d2 - d1
-    near = gap <= near_tie_rel * d2
+    near = np.isfinite(d2) & (gap <= near_tie_rel * d2)
     return dict(idx=idx, centroids=c, labels=labels, d1=d1, d2=d2, J=np.array(J),
                 iters=iters, converged=converged, empty=empty,
                 ties=int(np.count_nonzero(d1 == d2)), near_ties=int(near.sum()),

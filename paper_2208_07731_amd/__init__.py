@@ -1,0 +1,9 @@
+"""MI355X (gfx950) ISDF: weighted K-means interpolation points, least-squares
+interpolation vectors and their adjoint, after arXiv:2208.07731.
+
+The computation lives in libisdf.so (hand-written HIP kernels behind the C ABI
+of include/isdf.h); this package is the Python binding.
+"""
+from .api import ISDFError, KMeansResult, fit, fit_backward, kmeans  # noqa: F401
+
+__all__ = ["kmeans", "fit", "fit_backward", "ISDFError", "KMeansResult"]

@@ -1,0 +1,416 @@
+// Adjoint of the least-squares fit Theta = G M^-1 (eq. theta of
+// arXiv:2208.07731) with the interpolation points fixed.  The paper has no
+// adjoint; this is reverse-mode differentiation of the forward formulas, in
+// PyTorch's complex-gradient convention (dL/dRe + i dL/dIm):
+//
+//   S = Thetabar M^-1,  Mbar = -Theta^H S,  Gbar = S,  Gbar[idx] += Mbar,
+//   Abar = Gbar .* B,  Bbar = conj(Gbar) .* A,
+//   dPhi = Abar Phi_mu,  dPhi[idx] += Abar^H Phi,  (same for Psi with Bbar).
+//
+// Theta, G, A, B are recomputed one r-block at a time and never stored
+// whole.  Per block: Gram + Hadamard (A, B and G kept for the block), Theta
+// = G M^-1 and S = Thetabar M^-1 (FP64 GEMMs; with the fused loss
+// L = sum g |Theta|^2, Thetabar = 2 g Theta is folded into S as a row scale),
+// the split-K partials of Theta^T S and Abar^T Phi (reduced in a fixed
+// order, so the result is deterministic), Abar / Bbar in place, and the
+// block's rows of dPhi = Abar Phi_mu.  The Mbar terms touch only the N_mu
+// interpolation rows and are applied once after the last block.
+#include "fitlib.h"
+
+namespace isdf {
+namespace {
+
+constexpr int MAX_SPLITS = 16;
+
+// Abar / Bbar from S and the block's Gram blocks, in place.
+//  aliased: S real [R][n_mu]; A complex -> Abar = S A (over A)
+//  general: S complex; Abar = S B (over B), Bbar = conj(S) A (over A)
+__global__ void adj_hadamard(const double* __restrict__ S, double* __restrict__ A, double* __restrict__ B,
+                             int64_t R, int n_mu, int aliased) {
+  const int64_t total = R * n_mu;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double2* a = reinterpret_cast<double2*>(A) + e;
+    if (aliased) {
+      const double s = S[e];
+      double2 v = *a;
+      *a = make_double2(s * v.x, s * v.y);
+    } else {
+      const double2 s = reinterpret_cast<const double2*>(S)[e];
+      double2* b = reinterpret_cast<double2*>(B) + e;
+      const double2 av = *a, bv = *b;
+      *b = make_double2(s.x * bv.x - s.y * bv.y, s.x * bv.y + s.y * bv.x);
+      *a = make_double2(s.x * av.x + s.y * av.y, s.x * av.y - s.y * av.x);
+    }
+  }
+}
+
+// F[n][k] (n = 2 i + c', k = 2 nu + c): real form of right-multiplication by
+// Phi_mu, (x + iy)(a + ib) = (xa - yb) + i(xb + ya) with Phi_mu[nu][i] = a + ib.
+template <class TS, class T>
+__global__ void pack_adj_rhs(const TS* __restrict__ phi, int64_t ld, int n, const int32_t* __restrict__ idx,
+                             int n_mu, int64_t nr, T* __restrict__ F) {
+  const int64_t total = (int64_t)2 * n * 2 * n_mu;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / (2 * n_mu)), k = (int)(e % (2 * n_mu));
+    const int i = row >> 1, cp = row & 1, nu = k >> 1, c = k & 1;
+    int64_t p = idx[nu];
+    if (p < 0 || p >= nr) p = 0;
+    const double2 z = Cplx<TS>::load(phi + 2 * (p * ld + i));
+    double v;
+    if (cp == 0) v = c == 0 ? z.x : -z.y;
+    else v = c == 0 ? z.y : z.x;
+    F[e] = (T)v;
+  }
+}
+
+// Real rows of Phi at the interpolation points: X[mu][k] = Phi_real[idx[mu]][k].
+template <class TS, class T>
+__global__ void gather_rows(const TS* __restrict__ phi, int64_t ld, int n, const int32_t* __restrict__ idx,
+                            int n_mu, int64_t nr, T* __restrict__ X) {
+  const int64_t total = (int64_t)n_mu * 2 * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / (2 * n)), k = (int)(e % (2 * n));
+    int64_t p = idx[mu];
+    if (p < 0 || p >= nr) p = 0;
+    X[e] = (T)phi[2 * p * ld + k];
+  }
+}
+
+// out = (accumulate ? out : 0) + sum_z part[z] in increasing z.
+__global__ void reduce_splits(double* __restrict__ out, const double* __restrict__ part, int64_t n, int splits,
+                              int accumulate, const int* abort) {
+  if (*abort) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = accumulate ? out[i] : 0.0;
+    for (int z = 0; z < splits; ++z) s += part[z * n + i];
+    out[i] = s;
+  }
+}
+
+// Theta store + per-workgroup partial of sum_r g_r sum_c Theta_real[r][c]^2.
+struct EpiStoreLoss {
+  double* C;
+  int64_t ldc;
+  int M, N;
+  const double* g;
+  double* partial;
+  template <class Cfg, class Acc>
+  __device__ __forceinline__ void apply(const Acc (&acc)[Cfg::MI][Cfg::NI], const TileAt& at) const {
+    __shared__ double red[Cfg::THREADS / ISDF_WAVE];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j) {
+        const int n = at.n_wave + j * 16 + (at.lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
+          if (m < M && n < N) {
+            const double v = (double)acc[i][j][r];
+            C[(int64_t)m * ldc + n] = v;
+            s += g[m] * (v * v);
+          }
+        }
+      }
+    s = wave_sum(s);
+    if (at.lane == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < Cfg::THREADS / ISDF_WAVE; ++w) t += red[w];
+      partial[blockIdx.x] = t;
+    }
+  }
+};
+
+__global__ void add_loss(FitState* st, const double* __restrict__ partial, int n) {
+  if (st->abort) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += ISDF_WAVE) s += partial[i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) st->loss += s;
+}
+
+// Corrections at the interpolation rows from Mbar = -combine(P):
+//  aliased: dA = Mbar .* A_mu (Mbar real)
+//  general: Mbar_{mu nu} = -[(P_rr + P_ii) + i (P_ri - P_ir)],
+//           dA = Mbar .* B_mu, dB = conj(Mbar) .* A_mu
+__global__ void mbar_hadamard(const double* __restrict__ P, const double* __restrict__ Amu,
+                              const double* __restrict__ Bmu, double* __restrict__ dA, double* __restrict__ dB,
+                              int n_mu, int aliased, const int* abort) {
+  if (*abort) return;
+  const int64_t total = (int64_t)n_mu * n_mu;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / n_mu), nu = (int)(e % n_mu);
+    const double2 a = reinterpret_cast<const double2*>(Amu)[e];
+    if (aliased) {
+      const double m = -P[e];
+      reinterpret_cast<double2*>(dA)[e] = make_double2(m * a.x, m * a.y);
+    } else {
+      const int64_t n1 = 2 * (int64_t)n_mu;
+      const double prr = P[(2 * mu) * n1 + 2 * nu], pii = P[(2 * mu + 1) * n1 + 2 * nu + 1];
+      const double pri = P[(2 * mu) * n1 + 2 * nu + 1], pir = P[(2 * mu + 1) * n1 + 2 * nu];
+      const double mr = -(prr + pii), mi = -(pri - pir);
+      const double2 b = reinterpret_cast<const double2*>(Bmu)[e];
+      reinterpret_cast<double2*>(dA)[e] = make_double2(mr * b.x - mi * b.y, mr * b.y + mi * b.x);
+      reinterpret_cast<double2*>(dB)[e] = make_double2(mr * a.x + mi * a.y, mr * a.y - mi * a.x);
+    }
+  }
+}
+
+// dX[idx[mu]][i] += T1[mu][i] + (Abar^H X)[mu][i], the latter combined from
+// Q[2 mu + c][2 i + c'] = sum_r Abar_c(r, mu) X_c'(r, i).
+template <class TS>
+__global__ void scatter_rows(TS* __restrict__ dX, int64_t ld, int n, const int32_t* __restrict__ idx, int n_mu,
+                             const double* __restrict__ Q, const double* __restrict__ T1, const int* abort) {
+  if (*abort) return;
+  const int64_t total = (int64_t)n_mu * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int mu = (int)(e / n), i = (int)(e % n);
+    const int64_t q0 = (int64_t)(2 * mu) * (2 * n), q1 = q0 + 2 * n;
+    const double re = Q[q0 + 2 * i] + Q[q1 + 2 * i + 1] + T1[(int64_t)mu * 2 * n + 2 * i];
+    const double im = Q[q0 + 2 * i + 1] - Q[q1 + 2 * i] + T1[(int64_t)mu * 2 * n + 2 * i + 1];
+    TS* p = dX + 2 * ((int64_t)idx[mu] * ld + i);
+    const double2 old = Cplx<TS>::load(p);
+    Cplx<TS>::store(p, old.x + re, old.y + im);
+  }
+}
+
+template <class TS>
+__global__ void copy_rows(TS* __restrict__ dst, int64_t ldd, const TS* __restrict__ src, int64_t lds, int64_t rows,
+                          int n) {
+  const int64_t total = rows * 2 * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / (2 * n), k = e % (2 * n);
+    dst[2 * r * ldd + k] = src[2 * r * lds + k];
+  }
+}
+
+static unsigned blocks_for(int64_t n) {
+  int64_t b = ceil_div(n, 256);
+  return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+static int splits_for(int64_t tiles, int64_t K) {
+  int s = (int)(2048 / (tiles > 0 ? tiles : 1));
+  if (s > MAX_SPLITS) s = MAX_SPLITS;
+  const int64_t kmax = ceil_div(K, 512);
+  if (s > kmax) s = (int)kmax;
+  return s < 1 ? 1 : s;
+}
+
+struct BwdPlan {
+  FitState* st;
+  void *Ephi, *Epsi, *Fphi, *Fpsi, *Xphi, *Xpsi;
+  double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart;
+  size_t bytes;
+};
+
+static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bool aliased, size_t tsize,
+                        int64_t rblock) {
+  Carver c(ws, cap);
+  BwdPlan P{};
+  const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
+  const int64_t n1 = aliased ? n_mu : 2 * (int64_t)n_mu;
+  const int nmax = n_phi > n_psi ? n_phi : n_psi;
+  P.st = c.take<FitState>(1);
+  P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
+  P.Fphi = c.take<char>((size_t)2 * n_phi * 2 * n_mu * tsize);
+  P.Xphi = c.take<char>((size_t)n_mu * 2 * n_phi * tsize);
+  if (!aliased) {
+    P.Epsi = c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize);
+    P.Fpsi = c.take<char>((size_t)2 * n_psi * 2 * n_mu * tsize);
+    P.Xpsi = c.take<char>((size_t)n_mu * 2 * n_psi * tsize);
+  }
+  P.G = c.take<double>((size_t)rblock * n1);
+  P.Th = c.take<double>((size_t)rblock * n1);
+  P.A = c.take<double>((size_t)rblock * 2 * n_mu);
+  if (!aliased) P.B = c.take<double>((size_t)rblock * 2 * n_mu);
+  P.P = c.take<double>((size_t)n1 * n1);
+  P.Ppart = c.take<double>((size_t)MAX_SPLITS * n1 * n1);
+  P.Qphi = c.take<double>((size_t)2 * n_mu * 2 * n_phi);
+  if (!aliased) P.Qpsi = c.take<double>((size_t)2 * n_mu * 2 * n_psi);
+  P.Qpart = c.take<double>((size_t)MAX_SPLITS * 2 * n_mu * 2 * nmax);
+  P.Amu = c.take<double>((size_t)n_mu * 2 * n_mu);
+  if (!aliased) P.Bmu = c.take<double>((size_t)n_mu * 2 * n_mu);
+  P.dA = c.take<double>((size_t)n_mu * 2 * n_mu);
+  if (!aliased) P.dB = c.take<double>((size_t)n_mu * 2 * n_mu);
+  P.T1 = c.take<double>((size_t)n_mu * 2 * nmax);
+  P.lpart = c.take<double>((size_t)ceil_div(rblock, 128) * ceil_div(n1, 128));
+  P.bytes = c.used;
+  return P;
+}
+
+// One orbital set's share of the block: dX rows = Abar F, Q += Abar^T X.
+template <class T, class TS>
+static bool orbital_block(const double* Abar, int n_mu, const T* F, const TS* X, int64_t ld_x, int n, TS* dX,
+                          int64_t ld_dx, int64_t r, int rows, double* Q, double* Qpart, const int* ab,
+                          hipStream_t s) {
+  const int64_t two_mu = 2 * (int64_t)n_mu;
+  if (!tgemm<T, KC, KC>(rows, 2 * n, two_mu, Abar, two_mu, F, two_mu, dX + 2 * r * ld_dx, 2 * ld_dx, 1.0, 0.0, ab,
+                        s))
+    return false;
+  const int64_t tiles = ceil_div(two_mu, 128) * ceil_div(2 * n, 128);
+  const int sp = splits_for(tiles, rows);
+  const int64_t qn = two_mu * 2 * n;
+  if (!tgemm<T, XC, XC>((int)two_mu, 2 * n, rows, Abar, two_mu, X + 2 * r * ld_x, 2 * ld_x, Qpart, 2 * (int64_t)n,
+                        1.0, 0.0, ab, s, sp, qn))
+    return false;
+  hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(qn)), dim3(256), 0, s, Q, Qpart, qn, sp, r > 0 ? 1 : 0, ab);
+  return launch_ok();
+}
+
+// Mbar terms of one orbital set at the interpolation rows.
+template <class T, class TS>
+static bool orbital_fix(const double* dAbar, int n_mu, const T* F, const T* Xmu, int n, TS* dX, int64_t ld_dx,
+                        const int32_t* idx, double* Q, double* T1, const int* ab, hipStream_t s) {
+  const int64_t two_mu = 2 * (int64_t)n_mu;
+  if (!tgemm<T, KC, KC>(n_mu, 2 * n, two_mu, dAbar, two_mu, F, two_mu, T1, 2 * (int64_t)n, 1.0, 0.0, ab, s))
+    return false;
+  if (!tgemm<T, XC, XC>((int)two_mu, 2 * n, n_mu, dAbar, two_mu, Xmu, 2 * (int64_t)n, Q, 2 * (int64_t)n, 1.0, 1.0,
+                        ab, s))
+    return false;
+  hipLaunchKernelGGL(scatter_rows<TS>, dim3(blocks_for((int64_t)n_mu * n)), dim3(256), 0, s, dX, ld_dx, n, idx, n_mu,
+                     (const double*)Q, (const double*)T1, ab);
+  return launch_ok();
+}
+
+template <class T, class TS, class TT>
+static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                   bool aliased, const int32_t* idx, int n_mu, const double* minv, const TT* tbar, int64_t ld_tbar,
+                   const double* g, TS* dphi, int64_t ld_dphi, TS* dpsi, int64_t ld_dpsi, double* loss,
+                   int64_t rblock, isdf_fit_info* info, const BwdPlan& P, hipStream_t s) {
+  const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
+  const int n1 = aliased ? n_mu : 2 * n_mu;
+  const int* ab = &P.st->abort;
+  hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
+  T *Ephi = (T*)P.Ephi, *Fphi = (T*)P.Fphi, *Xphi = (T*)P.Xphi;
+  T *Epsi = aliased ? Ephi : (T*)P.Epsi, *Fpsi = aliased ? Fphi : (T*)P.Fpsi, *Xpsi = aliased ? Xphi : (T*)P.Xpsi;
+  if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
+  hipLaunchKernelGGL((pack_adj_rhs<TS, T>), dim3(blocks_for((int64_t)4 * n_phi * n_mu)), dim3(256), 0, s, phi,
+                     ld_phi, n_phi, idx, n_mu, nr, Fphi);
+  hipLaunchKernelGGL((gather_rows<TS, T>), dim3(blocks_for((int64_t)2 * n_phi * n_mu)), dim3(256), 0, s, phi,
+                     ld_phi, n_phi, idx, n_mu, nr, Xphi);
+  if (!aliased) {
+    if (!pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
+    hipLaunchKernelGGL((pack_adj_rhs<TS, T>), dim3(blocks_for((int64_t)4 * n_psi * n_mu)), dim3(256), 0, s, psi,
+                       ld_psi, n_psi, idx, n_mu, nr, Fpsi);
+    hipLaunchKernelGGL((gather_rows<TS, T>), dim3(blocks_for((int64_t)2 * n_psi * n_mu)), dim3(256), 0, s, psi,
+                       ld_psi, n_psi, idx, n_mu, nr, Xpsi);
+  }
+  if (!launch_ok()) return ISDF_E_HIP;
+  double* Abar = aliased ? P.A : P.B;  // after adj_hadamard
+  double* Bbar = P.A;
+  for (int64_t r = 0; r < nr; r += rblock) {
+    const int rows = (int)(nr - r < rblock ? nr - r : rblock);
+    // Gram blocks of the r-block: A (and B) kept, G for Theta
+    if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, r, rows, P.G,
+                     n1, aliased ? G_REAL : G_CPLX, ab, s, P.A, aliased ? nullptr : P.B))
+      return ISDF_E_HIP;
+    // Theta = G M^-1 (and the fused loss)
+    if (!tbar) {
+      EpiStoreLoss epi{P.Th, n1, rows, n1, g + r, P.lpart};
+      Operand<double> a{P.G, n1, nullptr}, b{minv, n1, nullptr};
+      if (!launch_gemm<double, 128, 128, 16, 2, 2, double, KC, double, KC, 1>(rows, n1, n1, a, b, a, b, 0, epi, 0, ab,
+                                                                             s))
+        return ISDF_E_HIP;
+      const int tiles = (int)(ceil_div(rows, 128) * ceil_div(n1, 128));
+      hipLaunchKernelGGL(add_loss, dim3(1), dim3(ISDF_WAVE), 0, s, P.st, (const double*)P.lpart, tiles);
+      // S = 2 g . (Theta M^-1), written over G
+      if (!dgemm<KC, KC, double>(rows, n1, n1, P.Th, n1, minv, n1, P.G, n1, 2.0, 0.0, 0, ab, s, g + r))
+        return ISDF_E_HIP;
+    } else {
+      if (!dgemm<KC, KC, double>(rows, n1, n1, P.G, n1, minv, n1, P.Th, n1, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
+      const int64_t ldt = aliased ? ld_tbar : 2 * ld_tbar;
+      if (!dgemm<KC, KC, double, TT>(rows, n1, n1, tbar + r * ldt, ldt, minv, n1, P.G, n1, 1.0, 0.0, 0, ab, s))
+        return ISDF_E_HIP;
+    }
+    // P += Theta^T S (split-K, fixed-order reduction)
+    {
+      const int64_t tiles = ceil_div(n1, 128) * ceil_div(n1, 128);
+      const int sp = splits_for(tiles, rows);
+      const int64_t pn = (int64_t)n1 * n1;
+      if (!tgemm<double, XC, XC>(n1, n1, rows, P.Th, n1, P.G, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn))
+        return ISDF_E_HIP;
+      hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, r > 0 ? 1 : 0,
+                         ab);
+    }
+    // Abar (and Bbar) in place
+    hipLaunchKernelGGL(adj_hadamard, dim3(blocks_for((int64_t)rows * n_mu)), dim3(256), 0, s, (const double*)P.G,
+                       P.A, P.B, (int64_t)rows, n_mu, aliased ? 1 : 0);
+    if (!launch_ok()) return ISDF_E_HIP;
+    if (!orbital_block<T, TS>(Abar, n_mu, Fphi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi, P.Qpart, ab, s))
+      return ISDF_E_HIP;
+    if (!aliased &&
+        !orbital_block<T, TS>(Bbar, n_mu, Fpsi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows, P.Qpsi, P.Qpart, ab, s))
+      return ISDF_E_HIP;
+  }
+  // Mbar terms at the interpolation rows
+  if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu, nullptr,
+                   n1, G_CPLX, ab, s, P.Amu, aliased ? nullptr : P.Bmu))
+    return ISDF_E_HIP;
+  hipLaunchKernelGGL(mbar_hadamard, dim3(blocks_for((int64_t)n_mu * n_mu)), dim3(256), 0, s, (const double*)P.P,
+                     (const double*)P.Amu, (const double*)P.Bmu, P.dA, P.dB, n_mu, aliased ? 1 : 0, ab);
+  if (!launch_ok()) return ISDF_E_HIP;
+  if (!orbital_fix<T, TS>(P.dA, n_mu, Fphi, Xphi, n_phi, dphi, ld_dphi, idx, P.Qphi, P.T1, ab, s)) return ISDF_E_HIP;
+  if (!aliased && !orbital_fix<T, TS>(P.dB, n_mu, Fpsi, Xpsi, n_psi, dpsi, ld_dpsi, idx, P.Qpsi, P.T1, ab, s))
+    return ISDF_E_HIP;
+  if (aliased && dpsi != dphi) {
+    hipLaunchKernelGGL((copy_rows<TS>), dim3(blocks_for(nr * 2 * n_phi)), dim3(256), 0, s, dpsi, ld_dpsi,
+                       (const TS*)dphi, ld_dphi, nr, n_phi);
+  }
+  hipLaunchKernelGGL(fit_finish, dim3(1), dim3(1), 0, s, P.st, info, loss, 1);
+  if (!launch_ok()) return ISDF_E_HIP;
+  return ISDF_OK;
+}
+
+}  // namespace
+}  // namespace isdf
+
+using namespace isdf;
+
+extern "C" size_t isdf_fit_backward_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                                              int32_t aliased, isdf_prec prec, int64_t rblock) {
+  if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
+  return plan_bwd(nullptr, 0, n_mu, n_phi, n_psi, aliased != 0, tsize_of(prec), rblock).bytes;
+}
+
+extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+                                 int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx,
+                                 int32_t n_mu, isdf_prec prec, const double* minv, const void* theta_bar,
+                                 int64_t ld_tbar, const double* g, void* dphi, int64_t ld_dphi, void* dpsi,
+                                 int64_t ld_dpsi, double* loss, int64_t rblock, isdf_fit_info* info, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  int64_t nr = 0;
+  if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
+  if (!minv || !info || !dphi || !dpsi || rblock <= 0) return ISDF_E_ARG;
+  if (!theta_bar && !g) return ISDF_E_ARG;
+  if (theta_bar && ld_tbar < n_mu) return ISDF_E_ARG;
+  if (ld_dphi < n_phi || ld_dpsi < n_psi) return ISDF_E_ARG;
+  if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
+  if (prec == ISDF_P_BF16X6 || prec == ISDF_P_FP16X3) return ISDF_E_UNSUPPORTED;
+  const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
+  if (!aliased && dphi == dpsi) return ISDF_E_ARG;
+  if (rblock > nr) rblock = nr;
+  BwdPlan P = plan_bwd(ws, ws_bytes, n_mu, n_phi, n_psi, aliased, tsize_of(prec), rblock);
+  if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ISDF_P_FP64)
+    return bwd_run<double, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
+                                           aliased, idx, n_mu, minv, (const double*)theta_bar, ld_tbar, g,
+                                           (double*)dphi, ld_dphi, (double*)dpsi, ld_dpsi, loss, rblock, info, P, s);
+  if (dt == ISDF_C128)
+    return bwd_run<float, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
+                                          aliased, idx, n_mu, minv, (const double*)theta_bar, ld_tbar, g,
+                                          (double*)dphi, ld_dphi, (double*)dpsi, ld_dpsi, loss, rblock, info, P, s);
+  return bwd_run<float, float, float>(nr, (const float*)phi, ld_phi, n_phi, (const float*)psi, ld_psi, n_psi, aliased,
+                                      idx, n_mu, minv, (const float*)theta_bar, ld_tbar, g, (float*)dphi, ld_dphi,
+                                      (float*)dpsi, ld_dpsi, loss, rblock, info, P, s);
+}

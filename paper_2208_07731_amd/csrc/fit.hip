@@ -1,0 +1,158 @@
+// Least-squares fit of the interpolation vectors (Sec. 2.1, eqs. decomMatrix,
+// theta, muRownuCol, muRownuColden and the solver of Sec. 2.4 of
+// arXiv:2208.07731):
+//
+//   Theta = G M^-1,  G = Z C^H = A .* conj(B),  A = Phi Phi_mu^H,  B = Psi Psi_mu^H,
+//   M = C C^H = G[idx, :]  (Hermitian positive definite).
+//
+// Complex arithmetic is carried as real GEMMs on MFMA:
+//  * Gram blocks: the orbital rows, read in place as real rows
+//    (re_0, im_0, re_1, im_1, ...), times a packed coefficient matrix E built
+//    from Phi_mu whose rows give Re A and Im A of the same column nu in two
+//    16-column blocks, so that one lane holds both and the Hadamard product
+//    with conj(B) happens in registers (epilogue), never in memory.
+//  * M and its inverse: the complex case uses the real 2x2-block form
+//    [[re, im], [-im, re]] of every entry, a real symmetric positive definite
+//    matrix of order 2 N_mu whose inverse is the block form of M^-1; the
+//    aliased case (Psi = Phi) is real from the start.
+//  * Cholesky M = L L^T (blocked, 64-wide diagonal blocks factored and
+//    inverted in LDS, panel and trailing updates on the FP64 GEMM), then
+//    L^-1 by block forward substitution and M^-1 = L^-T L^-1.
+//  * Theta rows = G rows times M^-1 (FP64 GEMM), one r-block at a time.
+#include "fitlib.h"
+
+namespace isdf {
+
+struct FitPlan {
+  FitState* st;
+  int* marker;
+  void* Ephi;
+  void* Epsi;
+  InvWork inv;
+  double* G;
+  size_t bytes;
+};
+
+static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, int n_psi, bool aliased,
+                        size_t tsize, int64_t rblock) {
+  Carver c(ws, cap);
+  FitPlan P{};
+  const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
+  const int n1 = aliased ? n_mu : 2 * n_mu;
+  const int nblk = (int)ceil_div(n1, NB);
+  P.st = c.take<FitState>(1);
+  P.marker = c.take<int>(nr);
+  P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
+  P.Epsi = aliased ? nullptr : c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize);
+  P.inv.dinv = c.take<double>((size_t)nblk * NB * NB);
+  P.inv.Y = c.take<double>((size_t)n1 * n1);
+  P.inv.R = c.take<double>((size_t)NB * n1);
+  P.G = c.take<double>((size_t)rblock * n1);
+  P.bytes = c.used;
+  return P;
+}
+
+static bool fit_args_ok(const isdf_grid* g, isdf_dtype dt, const void* phi, int64_t ld_phi, int n_phi,
+                        const void* psi, int64_t ld_psi, int n_psi, const int32_t* idx, int n_mu, isdf_prec prec,
+                        int64_t* nr_out) {
+  if (!g) return false;
+  for (int a = 0; a < 3; ++a)
+    if (g->n[a] <= 0) return false;
+  const int64_t nr = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  if (nr >= INT32_MAX) return false;
+  if (dt != ISDF_C128 && dt != ISDF_C64) return false;
+  if (!phi || !psi || !idx || n_phi <= 0 || n_psi <= 0 || ld_phi < n_phi || ld_psi < n_psi) return false;
+  if (n_mu <= 0 || n_mu > nr) return false;
+  if (prec < ISDF_P_FP64 || prec > ISDF_P_FP16X3) return false;
+  *nr_out = nr;
+  return true;
+}
+
+static size_t tsize_of(isdf_prec p) { return p == ISDF_P_FP64 ? sizeof(double) : sizeof(float); }
+
+template <class T, class TS, class TT>
+static int fit_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                   bool aliased, const int32_t* idx, int n_mu, double* minv, uint32_t flags, int64_t row0,
+                   int64_t nrows, TT* theta, int64_t ld_theta, int64_t rblock, isdf_fit_info* info,
+                   const FitPlan& P, hipStream_t s) {
+  const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
+  const int n1 = aliased ? n_mu : 2 * n_mu;
+  const int* ab = &P.st->abort;
+  hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
+  if (!launch_ok()) return ISDF_E_HIP;
+  T* Ephi = (T*)P.Ephi;
+  T* Epsi = aliased ? Ephi : (T*)P.Epsi;
+  if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
+  if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
+  if (flags & ISDF_FIT_FACTOR) {
+    if (!fill<int>(P.marker, nr, 0, s)) return ISDF_E_HIP;
+    hipLaunchKernelGGL(check_idx, dim3((unsigned)ceil_div(n_mu, 256)), dim3(256), 0, s, idx, n_mu, nr, P.marker,
+                       P.st);
+    if (!launch_ok()) return ISDF_E_HIP;
+    // M = C C^H: the Gram + Hadamard of the interpolation rows themselves
+    if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu, minv,
+                     n1, aliased ? G_REAL : G_EMB, ab, s))
+      return ISDF_E_HIP;
+    ISDF_TRY(spd_inverse(minv, n1, P.inv, P.st, s));
+  }
+  for (int64_t r = 0; r < nrows; r += rblock) {
+    const int rows = (int)(nrows - r < rblock ? nrows - r : rblock);
+    if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, row0 + r,
+                     rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s))
+      return ISDF_E_HIP;
+    const int64_t ldt = aliased ? ld_theta : 2 * ld_theta;
+    if (!dgemm<KC, KC, TT>(rows, n1, n1, P.G, n1, minv, n1, theta + r * ldt, ldt, 1.0, 0.0, 0, ab, s))
+      return ISDF_E_HIP;
+  }
+  hipLaunchKernelGGL(fit_finish, dim3(1), dim3(1), 0, s, P.st, info, (double*)nullptr, 0);
+  if (!launch_ok()) return ISDF_E_HIP;
+  return ISDF_OK;
+}
+
+}  // namespace isdf
+
+using namespace isdf;
+
+extern "C" size_t isdf_fit_minv_elems(int32_t n_mu, int32_t aliased) {
+  if (n_mu <= 0) return 0;
+  const size_t n1 = aliased ? (size_t)n_mu : 2 * (size_t)n_mu;
+  return n1 * n1;
+}
+
+extern "C" size_t isdf_fit_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                                     int32_t aliased, isdf_prec prec, int64_t rblock) {
+  if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  if (nr <= 0) return 0;
+  return plan_fit(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, tsize_of(prec), rblock).bytes;
+}
+
+extern "C" int isdf_fit(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+                        const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
+                        isdf_prec prec, double* minv, uint32_t flags, int64_t row0, int64_t nrows, void* theta,
+                        int64_t ld_theta, int64_t rblock, isdf_fit_info* info, void* ws, size_t ws_bytes,
+                        void* stream) {
+  int64_t nr = 0;
+  if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
+  if (flags & ~ISDF_FIT_FACTOR) return ISDF_E_ARG;
+  if (!minv || !info || (nrows > 0 && !theta) || row0 < 0 || nrows < 0 || row0 + nrows > nr) return ISDF_E_ARG;
+  if (ld_theta < n_mu || rblock <= 0) return ISDF_E_ARG;
+  if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
+  if (prec == ISDF_P_BF16X6 || prec == ISDF_P_FP16X3) return ISDF_E_UNSUPPORTED;
+  const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
+  FitPlan P = plan_fit(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, tsize_of(prec), rblock);
+  if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ISDF_P_FP64) {
+    return fit_run<double, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
+                                           aliased, idx, n_mu, minv, flags, row0, nrows, (double*)theta, ld_theta,
+                                           rblock, info, P, s);
+  }
+  if (dt == ISDF_C128)
+    return fit_run<float, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
+                                          aliased, idx, n_mu, minv, flags, row0, nrows, (double*)theta, ld_theta,
+                                          rblock, info, P, s);
+  return fit_run<float, float, float>(nr, (const float*)phi, ld_phi, n_phi, (const float*)psi, ld_psi, n_psi,
+                                      aliased, idx, n_mu, minv, flags, row0, nrows, (float*)theta, ld_theta, rblock,
+                                      info, P, s);
+}

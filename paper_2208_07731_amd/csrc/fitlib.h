@@ -1,0 +1,334 @@
+// Shared pieces of the fit and its adjoint: Gram + Hadamard GEMMs, the
+// FP64 Cholesky / inverse of C C^H, device state.  Everything here has
+// internal linkage (anonymous namespace) so that each translation unit gets
+// its own copy of the kernels.
+#pragma once
+#include <float.h>
+#include <limits.h>
+
+#include "gemm.h"
+
+namespace isdf {
+namespace {
+
+constexpr int NB = 64;  // Cholesky block
+
+struct FitState {
+  int abort;    // nonzero: later launches of this call are no-ops
+  int pivot;    // first failing pivot (INT_MAX: none)
+  int bad_idx;  // first invalid idx position (INT_MAX: none)
+  int pad;
+  double pmin, pmax;
+  double loss;
+};
+
+// ------------------------------------------------------------ idx checks
+__global__ void fit_state_init(FitState* st) {
+  st->abort = 0;
+  st->pivot = INT_MAX;
+  st->bad_idx = INT_MAX;
+  st->pad = 0;
+  st->pmin = INFINITY;
+  st->pmax = 0.0;
+  st->loss = 0.0;
+}
+
+__global__ void check_idx(const int32_t* __restrict__ idx, int n_mu, int64_t nr, int* __restrict__ marker,
+                          FitState* st) {
+  int mu = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mu >= n_mu) return;
+  int v = idx[mu];
+  bool bad = v < 0 || v >= nr;
+  if (!bad) bad = atomicAdd(&marker[v], 1) != 0;
+  if (bad) {
+    atomicMin(&st->bad_idx, mu);
+    atomicOr(&st->abort, 1);
+  }
+}
+
+// E[n][k], n = 32 b + 16 c + t -> column nu = 16 b + t, part c (0: Re A, 1: Im A);
+// k = 2 i + comp multiplies (re, im) of orbital i of the grid row.
+// With Phi_mu[nu][i] = a + i b:  Re A = sum x a + y b,  Im A = sum y a - x b.
+template <class TS, class T>
+__global__ void pack_gram_rhs(const TS* __restrict__ phi, int64_t ld, int n, const int32_t* __restrict__ idx,
+                              int n_mu, int64_t nr, int rows, T* __restrict__ E) {
+  const int64_t total = (int64_t)rows * 2 * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / (2 * n));
+    const int k = (int)(e % (2 * n));
+    const int b = r >> 5, c = (r >> 4) & 1, t = r & 15;
+    const int nu = b * 16 + t;
+    double v = 0.0;
+    if (nu < n_mu) {
+      int64_t p = idx[nu];
+      if (p < 0 || p >= nr) p = 0;  // invalid entries are reported by check_idx
+      const int i = k >> 1, comp = k & 1;
+      double2 z = Cplx<TS>::load(phi + 2 * (p * ld + i));
+      if (c == 0) v = comp == 0 ? z.x : z.y;
+      else v = comp == 0 ? -z.y : z.x;
+    }
+    E[e] = (T)v;
+  }
+}
+
+// Gram + Hadamard epilogue.  Accumulator pairs (j, j+1) of a wavefront hold
+// Re and Im of the same column nu.
+enum { G_REAL = 0, G_CPLX = 1, G_EMB = 2 };
+struct EpiGram {
+  double* G;  // may be null (only A / B wanted)
+  int64_t ldg;  // doubles
+  int M;
+  int n_mu;
+  int mode;
+  double* Aout;  // optional: A (and B) as interleaved complex rows, ld ldab doubles
+  double* Bout;
+  int64_t ldab;
+  template <class Cfg, class Acc>
+  __device__ __forceinline__ void apply(const Acc (&acc)[Cfg::MI][Cfg::NI], const TileAt& at) const {
+    // Psi = Phi: G = |A|^2 (real)
+#pragma unroll
+    for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+      for (int jp = 0; jp < Cfg::NI / 2; ++jp) {
+        const int nu = ((at.n_wave + 32 * jp) >> 5) * 16 + (at.lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
+          if (m < M && nu < n_mu) {
+            const double re = (double)acc[i][2 * jp][r], im = (double)acc[i][2 * jp + 1][r];
+            if (G) G[(int64_t)m * ldg + nu] = re * re + im * im;
+            if (Aout) *reinterpret_cast<double2*>(Aout + (int64_t)m * ldab + 2 * nu) = make_double2(re, im);
+          }
+        }
+      }
+  }
+  template <class Cfg, class Acc>
+  __device__ __forceinline__ void apply2(const Acc (&a)[Cfg::MI][Cfg::NI], const Acc (&b)[Cfg::MI][Cfg::NI],
+                                         const TileAt& at) const {
+    // G = A .* conj(B)
+#pragma unroll
+    for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+      for (int jp = 0; jp < Cfg::NI / 2; ++jp) {
+        const int nu = ((at.n_wave + 32 * jp) >> 5) * 16 + (at.lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
+          if (m < M && nu < n_mu) {
+            const double ar = (double)a[i][2 * jp][r], ai = (double)a[i][2 * jp + 1][r];
+            const double br = (double)b[i][2 * jp][r], bi = (double)b[i][2 * jp + 1][r];
+            const double x = ar * br + ai * bi, y = ai * br - ar * bi;
+            if (Aout) *reinterpret_cast<double2*>(Aout + (int64_t)m * ldab + 2 * nu) = make_double2(ar, ai);
+            if (Bout) *reinterpret_cast<double2*>(Bout + (int64_t)m * ldab + 2 * nu) = make_double2(br, bi);
+            if (!G) continue;
+            if (mode == G_CPLX) {
+              *reinterpret_cast<double2*>(G + (int64_t)m * ldg + 2 * nu) = make_double2(x, y);
+            } else {
+              *reinterpret_cast<double2*>(G + (int64_t)(2 * m) * ldg + 2 * nu) = make_double2(x, y);
+              *reinterpret_cast<double2*>(G + (int64_t)(2 * m + 1) * ldg + 2 * nu) = make_double2(-y, x);
+            }
+          }
+        }
+      }
+  }
+};
+
+// ------------------------------------------------------------ Cholesky
+// Factors the kb x kb diagonal block at (k0, k0) of X in place (lower), and
+// writes its inverse to dinv (kb x kb, ld NB) and to the diagonal block of Y.
+__global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ X, int64_t ldx, int k0, int kb,
+                                                  double* __restrict__ dinv, double* __restrict__ Y,
+                                                  int64_t ldy, FitState* st) {
+  if (st->abort) return;
+  __shared__ double a[NB][NB + 1];
+  __shared__ double li[NB][NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kb * kb; e += 256) {
+    const int i = e / kb, j = e % kb;
+    a[i][j] = j <= i ? X[(int64_t)(k0 + i) * ldx + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  int failed = -1;
+  for (int j = 0; j < kb; ++j) {
+    const double piv = a[j][j];
+    if (!(piv > 0.0) || !(piv < INFINITY)) {
+      failed = j;
+      break;
+    }
+    const double l = sqrt(piv);
+    __syncthreads();
+    if (tid == 0) {
+      a[j][j] = l;
+      atomic_min_pos(&st->pmin, piv);
+      atomic_max_pos(&st->pmax, piv);
+    }
+    for (int i = j + 1 + tid; i < kb; i += 256) a[i][j] /= l;
+    __syncthreads();
+    const int w = kb - j - 1;
+    for (int e = tid; e < w * w; e += 256) {
+      const int i = j + 1 + e / w, c = j + 1 + e % w;
+      if (c <= i) a[i][c] -= a[i][j] * a[c][j];
+    }
+    __syncthreads();
+  }
+  if (failed >= 0) {
+    if (tid == 0) {
+      atomicMin(&st->pivot, k0 + failed);
+      atomicOr(&st->abort, 1);
+    }
+    return;
+  }
+  for (int e = tid; e < kb * kb; e += 256) {
+    const int i = e / kb, j = e % kb;
+    if (j <= i) X[(int64_t)(k0 + i) * ldx + k0 + j] = a[i][j];
+  }
+  // inverse of the lower-triangular block, one column per thread
+  if (tid < kb) {
+    const int c = tid;
+    for (int i = 0; i < c; ++i) li[i][c] = 0.0;
+    for (int i = c; i < kb; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= a[i][k] * li[k][c];
+      li[i][c] = s / a[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kb * kb; e += 256) {
+    const int i = e / kb, j = e % kb;
+    dinv[i * NB + j] = li[i][j];
+    Y[(int64_t)(k0 + i) * ldy + k0 + j] = li[i][j];
+  }
+}
+
+__global__ void fit_finish(const FitState* st, isdf_fit_info* info, double* loss_out, int backward) {
+  int status = ISDF_OK;
+  if (st->bad_idx != INT_MAX) status = ISDF_E_BAD_IDX;
+  else if (st->pivot != INT_MAX) status = ISDF_E_NOT_PD;
+  else if (st->abort) status = ISDF_E_NONFINITE;
+  info->status = status;
+  info->pivot = st->pivot == INT_MAX ? -1 : st->pivot;
+  info->bad_idx = st->bad_idx == INT_MAX ? -1 : st->bad_idx;
+  info->reserved = 0;
+  info->pivot_min = st->pmin == INFINITY ? 0.0 : st->pmin;
+  info->pivot_max = st->pmax;
+  info->loss = st->loss;
+  if (backward && loss_out) *loss_out = st->loss;
+}
+
+// ------------------------------------------------------------ launches
+template <class T, int BM, int BN, int BK, int WM, int WN, class TA, int LA, class TB, int LB, int NOPS,
+          class Epi>
+static bool launch_gemm(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0, Operand<TA> A1,
+                        Operand<TB> B1, int64_t K1, const Epi& epi, int lower_only, const int* abort,
+                        hipStream_t st, int splits = 1) {
+  if (M <= 0 || N <= 0) return true;
+  GemmShape sh;
+  sh.M = M;
+  sh.N = N;
+  sh.K = K;
+  sh.kchunk = splits > 1 ? ceil_div(ceil_div(K, splits), BK) * BK : K;
+  sh.lower_only = lower_only;
+  sh.abort = abort;
+  const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
+  dim3 grid((unsigned)tiles, 1, (unsigned)splits);
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, TA, LA, TB, LB, NOPS, Epi>), grid,
+                     dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, epi);
+  return launch_ok();
+}
+
+// Plain FP64 GEMM C = alpha op(A) op(B) + beta C.
+template <int LA, int LB, class TC, class TA = double>
+static bool dgemm(int M, int N, int64_t K, const TA* A, int64_t lda, const double* B, int64_t ldb, TC* C,
+                  int64_t ldc, double alpha, double beta, int lower_only, const int* abort, hipStream_t st,
+                  const double* rowscale = nullptr) {
+  EpiStore<TC> epi{C, ldc, M, N, alpha, beta, rowscale, 0};
+  Operand<TA> a{A, lda, nullptr};
+  Operand<double> b{B, ldb, nullptr};
+  return launch_gemm<double, 128, 128, 16, 2, 2, TA, LA, double, LB, 1>(M, N, K, a, b, a, b, 0, epi, lower_only,
+                                                                       abort, st);
+}
+
+// GEMM in compute type T with split-K slices written to C + z * zstride.
+template <class T, int LA, int LB, class TA, class TB, class TC>
+static bool tgemm(int M, int N, int64_t K, const TA* A, int64_t lda, const TB* B, int64_t ldb, TC* C, int64_t ldc,
+                  double alpha, double beta, const int* abort, hipStream_t st, int splits = 1,
+                  int64_t zstride = 0) {
+  EpiStore<TC> epi{C, ldc, M, N, alpha, beta, nullptr, zstride};
+  Operand<TA> a{A, lda, nullptr};
+  Operand<TB> b{B, ldb, nullptr};
+  return launch_gemm<T, 128, 128, 16, 2, 2, TA, LA, TB, LB, 1>(M, N, K, a, b, a, b, 0, epi, 0, abort, st, splits);
+}
+
+// Cholesky of X (n x n, lower, in place) and W = X^-1 into X.
+struct InvWork {
+  double* dinv;  // [nblk][NB][NB]
+  double* Y;     // [n][n]
+  double* R;     // [NB][n]
+};
+
+static int spd_inverse(double* X, int n, InvWork w, FitState* st, hipStream_t s) {
+  const int* ab = &st->abort;
+  const int nblk = (int)ceil_div(n, NB);
+  if (!fill<double>(w.Y, (int64_t)n * n, 0.0, s)) return ISDF_E_HIP;
+  for (int b = 0; b < nblk; ++b) {
+    const int k0 = b * NB, kb = n - k0 < NB ? n - k0 : NB;
+    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, X, (int64_t)n, k0, kb, w.dinv + (int64_t)b * NB * NB,
+                       w.Y, (int64_t)n, st);
+    if (!launch_ok()) return ISDF_E_HIP;
+    const int rest = n - k0 - kb;
+    if (rest <= 0) continue;
+    double* P = X + (int64_t)(k0 + kb) * n + k0;
+    // panel: L21 = A21 L11^-T (in place: each workgroup reads all K of its rows before writing them)
+    if (!dgemm<KC, KC>(rest, kb, kb, P, n, w.dinv + (int64_t)b * NB * NB, NB, P, n, 1.0, 0.0, 0, ab, s))
+      return ISDF_E_HIP;
+    // trailing: A22 -= L21 L21^T (lower tiles)
+    double* T = X + (int64_t)(k0 + kb) * n + (k0 + kb);
+    if (!dgemm<KC, KC>(rest, rest, kb, P, n, P, n, T, n, -1.0, 1.0, 1, ab, s)) return ISDF_E_HIP;
+  }
+  // Y = L^-1 by block rows: Y_i,<i = -Dinv_i (L_i,<i Y_<i,<i)
+  for (int b = 1; b < nblk; ++b) {
+    const int k0 = b * NB, kb = n - k0 < NB ? n - k0 : NB;
+    if (!dgemm<KC, XC>(kb, k0, k0, X + (int64_t)k0 * n, n, w.Y, n, w.R, n, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
+    if (!dgemm<KC, XC>(kb, k0, kb, w.dinv + (int64_t)b * NB * NB, NB, w.R, n, w.Y + (int64_t)k0 * n, n, -1.0, 0.0,
+                       0, ab, s))
+      return ISDF_E_HIP;
+  }
+  // W = Y^T Y
+  if (!dgemm<XC, XC>(n, n, n, w.Y, n, w.Y, n, X, n, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
+  return ISDF_OK;
+}
+
+// Gram + Hadamard of `rows` orbital rows (gathered through `gather` if
+// non-null, else starting at row r0) into G.
+template <class T, class TS>
+static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                 bool aliased, const T* Ephi, const T* Epsi, int nmu16, int n_mu, const int* gather, int64_t r0,
+                 int rows, double* G, int64_t ldg, int mode, const int* abort, hipStream_t s,
+                 double* Aout = nullptr, double* Bout = nullptr) {
+  EpiGram epi{G, ldg, rows, n_mu, mode, Aout, Bout, 2 * (int64_t)n_mu};
+  const int N = 2 * nmu16;
+  Operand<TS> a0{phi + 2 * r0 * ld_phi, 2 * ld_phi, gather};
+  Operand<T> b0{Ephi, 2 * (int64_t)n_phi, nullptr};
+  if (aliased)
+    return launch_gemm<T, 128, 128, 16, 2, 2, TS, KC, T, KC, 1>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0, 0,
+                                                                 epi, 0, abort, s);
+  Operand<TS> a1{psi + 2 * r0 * ld_psi, 2 * ld_psi, gather};
+  Operand<T> b1{Epsi, 2 * (int64_t)n_psi, nullptr};
+  return launch_gemm<T, 128, 64, 16, 2, 2, TS, KC, T, KC, 2>(rows, N, 2 * (int64_t)n_phi, a0, b0, a1, b1,
+                                                              2 * (int64_t)n_psi, epi, 0, abort, s);
+}
+
+template <class TS, class T>
+static bool pack(const TS* phi, int64_t ld, int n, const int* idx, int n_mu, int64_t nr, int nmu16, T* E,
+                 hipStream_t s) {
+  const int64_t total = (int64_t)2 * nmu16 * 2 * n;
+  int64_t blocks = ceil_div(total, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((pack_gram_rhs<TS, T>), dim3((unsigned)blocks), dim3(256), 0, s, phi, ld, n, idx, n_mu, nr,
+                     2 * nmu16, E);
+  return launch_ok();
+}
+
+}  // namespace
+}  // namespace isdf

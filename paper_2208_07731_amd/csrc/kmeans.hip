@@ -1,0 +1,543 @@
+// Weighted K-means over grid points (Sec. 2.2 and Alg. 1 of arXiv:2208.07731)
+// and the K-means weight functions (eqs. weight function, weight function 2).
+//
+// Kernels, in launch order:
+//   km_weight  one HBM pass over the orbital rows -> w[N_r] (FP64)
+//   km_init    seeds, counters and per-cluster bounding boxes
+//   km_assign  classification: argmin over centroids staged in LDS, one
+//              4x4x4 brick of grid points per wavefront; also the objective
+//              partials, tie counts, changed-label count and per-cluster
+//              bounding boxes (integer atomics, order independent)
+//   km_update  weighted centroids: one wavefront per cluster scans its
+//              bounding box in a fixed order -> deterministic FP64 sums
+//   km_snap    member nearest to each final centroid (lowest index on ties)
+//   km_final   info struct
+// A round that changes no label sets a device flag that turns the remaining
+// launches into no-ops, so the host enqueues a fixed sequence and never
+// synchronises.
+#include <float.h>
+#include <limits.h>
+
+#include "common.h"
+
+namespace isdf {
+
+struct KmState {
+  int done;        // remaining rounds are no-ops
+  int converged;
+  int iters;       // updates applied
+  int last_t;      // last classification that ran
+  int nonfinite;
+  int empty_final;
+  int pad0, pad1;
+};
+
+struct KmArrays {
+  KmState* st;
+  int* changed;    // [T+1]
+  int* ties;       // [T+1]
+  int* nearc;      // [T+1]
+  int* empty;      // [T+1]
+  double* jhist;   // [T+1]
+  double* cent;    // [K][3]
+  int* labels;     // [N_r]
+  double* w;       // [N_r]
+  int* bbox;       // [K][6]: imin, imax, jmin, jmax, kmin, kmax
+  double* jpart;   // [assign blocks]
+};
+
+struct KmGeom {
+  int n0, n1, n2;
+  int nb0, nb1, nb2;  // bricks per axis (4 points each)
+  double s0, s1, s2;  // metric weights (h_a / min h)^2
+  int aniso;
+};
+
+constexpr int ASSIGN_THREADS = 256;  // 4 wavefronts = 4 bricks
+constexpr int CTILE = 1024;          // centroids staged per LDS tile
+
+// Squared distance with the same operation order as the definition
+// ((s0 dx^2 + s1 dy^2) + s2 dz^2); contraction off so that the value is the
+// correctly rounded result of each operation.
+__device__ __forceinline__ double sqd(double dx, double dy, double dz, const KmGeom& g) {
+#pragma clang fp contract(off)
+  if (g.aniso) return (g.s0 * (dx * dx) + g.s1 * (dy * dy)) + g.s2 * (dz * dz);
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// ------------------------------------------------------------------ weight
+template <class T>
+__device__ __forceinline__ double row_pow_sum(const T* __restrict__ row, int n, int sub, int sw,
+                                              int alpha) {
+  double acc = 0.0;
+  for (int i = sub; i < n; i += sw) {
+    double2 z = Cplx<T>::load(row + 2 * (int64_t)i);
+    double s = z.x * z.x + z.y * z.y;
+    double v;
+    if (alpha == 2) v = s;
+    else if (alpha == 1) v = sqrt(s);
+    else if (alpha == 3) v = s * sqrt(s);
+    else v = s * s;
+    acc += v;
+  }
+  return acc;
+}
+
+// Segmented sum over `sw` consecutive lanes (sw a power of two <= 64).
+__device__ __forceinline__ double seg_sum(double v, int sw) {
+  for (int o = sw >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, ISDF_WAVE);
+  return v;
+}
+
+// Sub-wave of width sw per row; alpha = 2 for SSM/PSM.
+template <class T>
+__global__ __launch_bounds__(256) void km_weight(const T* __restrict__ phi, int64_t ldp, int nphi,
+                                                 const T* __restrict__ psi, int64_t lds, int npsi,
+                                                 int aliased, int kind, int sw, int64_t nr,
+                                                 double* __restrict__ w, KmState* st) {
+  const int lane = threadIdx.x & 63;
+  const int sub = lane & (sw - 1);
+  const int rows_per_wave = ISDF_WAVE / sw;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int alpha = kind == ISDF_W_SM ? 1 : kind == ISDF_W_SCM ? 3 : kind == ISDF_W_SQM ? 4 : 2;
+  int bad = 0;
+  for (int64_t r0 = wave * rows_per_wave; r0 < nr; r0 += nwaves * rows_per_wave) {
+    int64_t r = r0 + lane / sw;
+    double a = 0.0, b = 0.0;
+    if (r < nr) {
+      a = row_pow_sum<T>(phi + 2 * r * ldp, nphi, sub, sw, alpha);
+      if (!aliased) b = row_pow_sum<T>(psi + 2 * r * lds, npsi, sub, sw, alpha);
+    }
+    a = seg_sum(a, sw);
+    if (!aliased) b = seg_sum(b, sw);
+    if (aliased) b = a;
+    double v = kind == ISDF_W_PSM ? a * b : a + b;
+    if (r < nr && sub == 0) {
+      w[r] = v;
+      if (!isfinite(v)) bad = 1;
+    }
+  }
+  if (bad) atomicOr(&st->nonfinite, 1);
+}
+
+// Checks a caller-given weight for NaN / Inf / negative values.
+__global__ void km_check_weight(const double* __restrict__ w, int64_t nr, KmState* st) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nr;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = w[i];
+    if (!isfinite(v) || v < 0.0) bad = 1;
+  }
+  if (bad) atomicOr(&st->nonfinite, 1);
+}
+
+// ------------------------------------------------------------------ init
+__global__ void km_init(KmArrays a, const double* __restrict__ c0, int K, int T, int64_t nr) {
+  int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (tid == 0) {
+    int nf = a.st->nonfinite;  // written by the weight pass before this launch
+    a.st->done = nf ? 1 : 0;
+    a.st->converged = 0;
+    a.st->iters = 0;
+    a.st->last_t = -1;
+    a.st->empty_final = 0;
+  }
+  for (int64_t i = tid; i <= T; i += stride) {
+    a.changed[i] = 0;
+    a.ties[i] = 0;
+    a.nearc[i] = 0;
+    a.empty[i] = 0;
+    a.jhist[i] = -1.0;
+  }
+  for (int64_t i = tid; i < 3 * (int64_t)K; i += stride) a.cent[i] = c0[i];
+  for (int64_t i = tid; i < K; i += stride) {
+    int* b = a.bbox + 6 * i;
+    b[0] = INT_MAX; b[1] = INT_MIN; b[2] = INT_MAX; b[3] = INT_MIN; b[4] = INT_MAX; b[5] = INT_MIN;
+  }
+  for (int64_t i = tid; i < nr; i += stride) a.labels[i] = -1;
+}
+
+// ------------------------------------------------------------------ assign
+__global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g, int K, int t,
+                                                            double near_rel) {
+  if (a.st->done) return;
+  __shared__ double cx[CTILE], cy[CTILE], cz[CTILE];
+  __shared__ double jw[ASSIGN_THREADS / ISDF_WAVE];
+
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t brick = (int64_t)blockIdx.x * (ASSIGN_THREADS / ISDF_WAVE) + wv;
+  const int64_t nbricks = (int64_t)g.nb0 * g.nb1 * g.nb2;
+  int bi = 0, bj = 0, bk = 0;
+  if (brick < nbricks) {
+    bk = (int)(brick % g.nb2);
+    int64_t q = brick / g.nb2;
+    bj = (int)(q % g.nb1);
+    bi = (int)(q / g.nb1);
+  }
+  const int pi = bi * 4 + (lane >> 4), pj = bj * 4 + ((lane >> 2) & 3), pk = bk * 4 + (lane & 3);
+  const bool valid = brick < nbricks && pi < g.n0 && pj < g.n1 && pk < g.n2;
+  const double px = (double)pi, py = (double)pj, pz = (double)pk;
+
+  double d1 = DBL_MAX, d2 = DBL_MAX;
+  int lab = 0;
+  bool first = true;
+  for (int c0 = 0; c0 < K; c0 += CTILE) {
+    const int cn = min(CTILE, K - c0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cn; i += ASSIGN_THREADS) {
+      cx[i] = a.cent[3 * (int64_t)(c0 + i) + 0];
+      cy[i] = a.cent[3 * (int64_t)(c0 + i) + 1];
+      cz[i] = a.cent[3 * (int64_t)(c0 + i) + 2];
+    }
+    __syncthreads();
+    int m = 0;
+    if (first) {  // d1 <- centroid 0, so that DBL_MAX never masks a real distance
+      d1 = sqd(px - cx[0], py - cy[0], pz - cz[0], g);
+      d2 = INFINITY;
+      lab = 0;
+      m = 1;
+      first = false;
+    }
+#pragma unroll 4
+    for (; m < cn; ++m) {
+      double d = sqd(px - cx[m], py - cy[m], pz - cz[m], g);
+      d2 = fmin(d2, fmax(d, d1));
+      bool better = d < d1;
+      d1 = better ? d : d1;
+      lab = better ? c0 + m : lab;
+    }
+  }
+
+  const int64_t p = ((int64_t)pi * g.n1 + pj) * g.n2 + pk;
+  double jv = 0.0;
+  bool chg = false, tie = false, nr_tie = false;
+  if (valid) {
+    int old = a.labels[p];
+    chg = old != lab;
+    a.labels[p] = lab;
+    jv = a.w[p] * d1;
+    tie = d1 == d2;
+    nr_tie = (d2 < INFINITY) && (d2 - d1 <= near_rel * d2);
+  }
+  // objective partial: fixed-order block sum
+  jv = wave_sum(jv);
+  if (lane == 0) jw[wv] = jv;
+  unsigned long long bc = __ballot(chg), bt = __ballot(tie), bn = __ballot(nr_tie);
+  if (lane == 0) {
+    if (bc) atomicAdd(&a.changed[t], __popcll(bc));
+    if (bt) atomicAdd(&a.ties[t], __popcll(bt));
+    if (bn) atomicAdd(&a.nearc[t], __popcll(bn));
+  }
+  // per-cluster bounding boxes: one atomic set per distinct label in the brick
+  unsigned long long act = __ballot(valid);
+  while (act) {
+    int leader = __ffsll((long long)act) - 1;
+    int L = __shfl(lab, leader, ISDF_WAVE);
+    bool mine = valid && lab == L;
+    unsigned long long mm = __ballot(mine);
+    int imin = wave_min_i(mine ? pi : INT_MAX), imax = wave_max_i(mine ? pi : INT_MIN);
+    int jmin = wave_min_i(mine ? pj : INT_MAX), jmax = wave_max_i(mine ? pj : INT_MIN);
+    int kmin = wave_min_i(mine ? pk : INT_MAX), kmax = wave_max_i(mine ? pk : INT_MIN);
+    if (lane == leader) {
+      int* b = a.bbox + 6 * (int64_t)L;
+      atomicMin(b + 0, imin); atomicMax(b + 1, imax);
+      atomicMin(b + 2, jmin); atomicMax(b + 3, jmax);
+      atomicMin(b + 4, kmin); atomicMax(b + 5, kmax);
+    }
+    act &= ~mm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < ASSIGN_THREADS / ISDF_WAVE; ++i) s += jw[i];
+    a.jpart[blockIdx.x] = s;
+    if (blockIdx.x == 0) a.st->last_t = t;
+  }
+}
+
+// Fixed-order sum of the objective partials by one wavefront.
+__device__ double reduce_jpart(const double* __restrict__ jp, int n, int lane) {
+  double s = 0.0;
+  for (int i = lane; i < n; i += ISDF_WAVE) s += jp[i];
+  return wave_sum(s);
+}
+
+// Walks the bounding box of cluster `mu` line by line (lines along the last
+// axis); calls f(p, i, j, k) for every grid point of the box, each lane a
+// fixed subset in a fixed order.
+template <class F>
+__device__ __forceinline__ void scan_bbox(const int* b, const KmGeom& g, int lane, F&& f) {
+  const int i0 = b[0], i1 = b[1], j0 = b[2], j1 = b[3], k0 = b[4], k1 = b[5];
+  if (i0 > i1) return;
+  const int ej = j1 - j0 + 1, ek = k1 - k0 + 1;
+  const int64_t nlines = (int64_t)(i1 - i0 + 1) * ej;
+  if (ek <= ISDF_WAVE) {
+    const int lpp = ISDF_WAVE / ek;  // lines per pass
+    const int lo = lane / ek, kk = lane - lo * ek;
+    if (lo >= lpp) return;
+    for (int64_t q = lo; q < nlines; q += lpp) {
+      int i = i0 + (int)(q / ej), j = j0 + (int)(q % ej), k = k0 + kk;
+      f(((int64_t)i * g.n1 + j) * g.n2 + k, i, j, k);
+    }
+  } else {
+    for (int64_t q = 0; q < nlines; ++q) {
+      int i = i0 + (int)(q / ej), j = j0 + (int)(q % ej);
+      for (int k = k0 + lane; k <= k1; k += ISDF_WAVE) f(((int64_t)i * g.n1 + j) * g.n2 + k, i, j, k);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ update
+__global__ __launch_bounds__(256) void km_update(KmArrays a, KmGeom g, int K, int t, int nparts) {
+  if (a.st->done) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  if (blockIdx.x == 0 && wv == 0) {
+    double J = reduce_jpart(a.jpart, nparts, lane);
+    if (lane == 0) a.jhist[t] = J;
+  }
+  if (t > 0 && a.changed[t] == 0) {  // fixed point: same labels as the previous round
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.st->done = 1;
+      a.st->converged = 1;
+    }
+    return;
+  }
+  const int mu = blockIdx.x * 4 + wv;
+  if (mu >= K) return;
+  int* b = a.bbox + 6 * (int64_t)mu;
+  double sw = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  scan_bbox(b, g, lane, [&](int64_t p, int i, int j, int k) {
+    if (a.labels[p] == mu) {
+      double wp = a.w[p];
+      sw += wp;
+      sx += wp * (double)i;
+      sy += wp * (double)j;
+      sz += wp * (double)k;
+    }
+  });
+  sw = wave_sum(sw);
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  sz = wave_sum(sz);
+  if (lane == 0) {
+    if (sw > 0.0) {
+      a.cent[3 * (int64_t)mu + 0] = sx / sw;
+      a.cent[3 * (int64_t)mu + 1] = sy / sw;
+      a.cent[3 * (int64_t)mu + 2] = sz / sw;
+    } else {
+      atomicAdd(&a.empty[t], 1);
+    }
+    b[0] = INT_MAX; b[1] = INT_MIN; b[2] = INT_MAX; b[3] = INT_MIN; b[4] = INT_MAX; b[5] = INT_MIN;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.st->iters = t + 1;
+}
+
+// ------------------------------------------------------------------ snap
+__global__ __launch_bounds__(256) void km_snap(KmArrays a, KmGeom g, int K, int32_t* __restrict__ idx) {
+  const int lane = threadIdx.x & 63;
+  const int mu = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (mu >= K) return;
+  if (a.st->nonfinite) {
+    if (lane == 0) idx[mu] = -1;
+    return;
+  }
+  const double cxm = a.cent[3 * (int64_t)mu], cym = a.cent[3 * (int64_t)mu + 1],
+               czm = a.cent[3 * (int64_t)mu + 2];
+  double bd = INFINITY;
+  int64_t bp = -1;
+  scan_bbox(a.bbox + 6 * (int64_t)mu, g, lane, [&](int64_t p, int i, int j, int k) {
+    if (a.labels[p] == mu) {
+      double d = sqd((double)i - cxm, (double)j - cym, (double)k - czm, g);
+      if (d < bd || (d == bd && p < bp)) {
+        bd = d;
+        bp = p;
+      }
+    }
+  });
+  for (int o = 32; o > 0; o >>= 1) {
+    double od = __shfl_xor(bd, o, ISDF_WAVE);
+    int64_t op = __shfl_xor(bp, o, ISDF_WAVE);
+    bool take = (op >= 0) && (bp < 0 || od < bd || (od == bd && op < bp));
+    bd = take ? od : bd;
+    bp = take ? op : bp;
+  }
+  if (lane == 0) {
+    idx[mu] = (int32_t)bp;
+    if (bp < 0) atomicAdd(&a.st->empty_final, 1);
+  }
+}
+
+__global__ void km_final(KmArrays a, int nparts, isdf_kmeans_info* info, double* __restrict__ objective,
+                         int T) {
+  const int lane = threadIdx.x;
+  KmState* st = a.st;
+  int t = st->last_t;
+  double J = reduce_jpart(a.jpart, nparts, lane);
+  if (t >= 0 && lane == 0) a.jhist[t] = J;
+  if (objective)
+    for (int i = lane; i <= T; i += ISDF_WAVE) objective[i] = (i == t) ? J : a.jhist[i];
+  if (lane != 0) return;
+  int status = ISDF_OK;
+  if (st->nonfinite) status = ISDF_E_NONFINITE;
+  else if (st->empty_final) status = ISDF_W_EMPTY_CLUSTER;
+  info->status = status;
+  info->iters = st->iters;
+  info->converged = st->converged;
+  info->empty_update = st->iters > 0 ? a.empty[st->iters - 1] : 0;
+  info->empty_final = st->empty_final;
+  info->ties = t >= 0 ? a.ties[t] : 0;
+  info->near_ties = t >= 0 ? a.nearc[t] : 0;
+  info->changed = t >= 0 ? a.changed[t] : 0;
+  info->objective = t >= 0 ? J : 0.0;
+}
+
+__global__ void copy_f64(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ host
+struct KmPlan {
+  KmArrays a;
+  size_t bytes;
+};
+
+static KmPlan plan_kmeans(void* ws, size_t cap, int64_t nr, int K, int T, int nparts,
+                          bool own_cent, bool own_labels, bool own_w, bool own_obj) {
+  Carver c(ws, cap);
+  KmPlan P{};
+  P.a.st = c.take<KmState>(1);
+  P.a.changed = c.take<int>(T + 1);
+  P.a.ties = c.take<int>(T + 1);
+  P.a.nearc = c.take<int>(T + 1);
+  P.a.empty = c.take<int>(T + 1);
+  P.a.jhist = c.take<double>(T + 1);
+  P.a.bbox = c.take<int>(6 * (size_t)K);
+  P.a.jpart = c.take<double>(nparts);
+  if (own_cent) P.a.cent = c.take<double>(3 * (size_t)K);
+  if (own_labels) P.a.labels = c.take<int>(nr);
+  if (own_w) P.a.w = c.take<double>(nr);
+  (void)own_obj;
+  P.bytes = c.used;
+  return P;
+}
+
+static KmGeom make_geom(const isdf_grid* g) {
+  KmGeom G{};
+  G.n0 = g->n[0];
+  G.n1 = g->n[1];
+  G.n2 = g->n[2];
+  G.nb0 = (G.n0 + 3) / 4;
+  G.nb1 = (G.n1 + 3) / 4;
+  G.nb2 = (G.n2 + 3) / 4;
+  double hmin = fmin(g->h[0], fmin(g->h[1], g->h[2]));
+  G.s0 = (g->h[0] / hmin) * (g->h[0] / hmin);
+  G.s1 = (g->h[1] / hmin) * (g->h[1] / hmin);
+  G.s2 = (g->h[2] / hmin) * (g->h[2] / hmin);
+  G.aniso = !(G.s0 == 1.0 && G.s1 == 1.0 && G.s2 == 1.0);
+  return G;
+}
+
+static int assign_blocks(const KmGeom& G) {
+  int64_t nb = (int64_t)G.nb0 * G.nb1 * G.nb2;
+  return (int)ceil_div(nb, ASSIGN_THREADS / ISDF_WAVE);
+}
+
+static bool grid_ok(const isdf_grid* g) {
+  if (!g) return false;
+  for (int a = 0; a < 3; ++a) {
+    if (g->n[a] <= 0) return false;
+    if (!(g->h[a] > 0.0) || !(g->h[a] < 1e300)) return false;
+  }
+  int64_t nr = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  return nr < (int64_t)INT32_MAX;
+}
+
+}  // namespace isdf
+
+using namespace isdf;
+
+extern "C" size_t isdf_kmeans_workspace(const isdf_grid* grid, int32_t n_mu, int32_t max_iter) {
+  if (!grid_ok(grid) || n_mu <= 0 || max_iter < 0) return 0;
+  int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  KmGeom G = make_geom(grid);
+  return plan_kmeans(nullptr, 0, nr, n_mu, max_iter, assign_blocks(G), true, true, true, true).bytes;
+}
+
+extern "C" int isdf_kmeans(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+                           int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
+                           int32_t weight_kind, uint32_t flags, int32_t n_mu, const double* c0,
+                           int32_t max_iter, double near_tie_rel, int32_t* idx, double* centroids,
+                           int32_t* labels, double* w, double* objective, isdf_kmeans_info* info,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (!grid_ok(grid)) return ISDF_E_ARG;
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  const bool wgiven = (flags & ISDF_KM_WEIGHT_GIVEN) != 0;
+  if (flags & ~ISDF_KM_WEIGHT_GIVEN) return ISDF_E_ARG;
+  if (n_mu <= 0 || n_mu > nr || max_iter < 0 || !c0 || !idx || !info) return ISDF_E_ARG;
+  if (!(near_tie_rel >= 0.0)) return ISDF_E_ARG;
+  if (wgiven) {
+    if (!w) return ISDF_E_ARG;
+  } else {
+    if (dt != ISDF_C128 && dt != ISDF_C64) return ISDF_E_ARG;
+    if (weight_kind < ISDF_W_SSM || weight_kind > ISDF_W_SQM) return ISDF_E_ARG;
+    if (!phi || !psi || n_phi <= 0 || n_psi <= 0 || ld_phi < n_phi || ld_psi < n_psi) return ISDF_E_ARG;
+  }
+  KmGeom G = make_geom(grid);
+  const int nparts = assign_blocks(G);
+  KmPlan P = plan_kmeans(ws, ws_bytes, nr, n_mu, max_iter, nparts, !centroids, !labels, !w, !objective);
+  if (P.bytes > ws_bytes || !ws) return ISDF_E_WORKSPACE;
+  if (centroids) P.a.cent = centroids;
+  if (labels) P.a.labels = labels;
+  if (w) P.a.w = w;
+  hipStream_t st = (hipStream_t)stream;
+
+  // state must be clean before the weight pass can flag non-finite values
+  if (!fill<int>((int*)P.a.st, sizeof(KmState) / sizeof(int), 0, st)) return ISDF_E_HIP;
+  if (!wgiven) {
+    const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
+    int nmax = aliased ? n_phi : (n_phi > n_psi ? n_phi : n_psi);
+    int sw = 64;
+    while (sw > 1 && sw / 2 >= nmax) sw >>= 1;
+    int64_t rows_per_block = (256 / 64) * (64 / sw);
+    int64_t blocks = ceil_div(nr, rows_per_block);
+    if (blocks > 8192) blocks = 8192;
+    if (dt == ISDF_C128)
+      hipLaunchKernelGGL(km_weight<double>, dim3((unsigned)blocks), dim3(256), 0, st, (const double*)phi,
+                         ld_phi, n_phi, (const double*)psi, ld_psi, n_psi, aliased ? 1 : 0, weight_kind, sw,
+                         nr, P.a.w, P.a.st);
+    else
+      hipLaunchKernelGGL(km_weight<float>, dim3((unsigned)blocks), dim3(256), 0, st, (const float*)phi, ld_phi,
+                         n_phi, (const float*)psi, ld_psi, n_psi, aliased ? 1 : 0, weight_kind, sw, nr,
+                         P.a.w, P.a.st);
+    if (!launch_ok()) return ISDF_E_HIP;
+  } else {
+    int64_t blocks = ceil_div(nr, 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(km_check_weight, dim3((unsigned)blocks), dim3(256), 0, st, (const double*)P.a.w, nr,
+                       P.a.st);
+    if (!launch_ok()) return ISDF_E_HIP;
+  }
+  {
+    int64_t work = nr > 3 * (int64_t)n_mu ? nr : 3 * (int64_t)n_mu;
+    int64_t blocks = ceil_div(work, 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(km_init, dim3((unsigned)blocks), dim3(256), 0, st, P.a, c0, n_mu, max_iter, nr);
+    if (!launch_ok()) return ISDF_E_HIP;
+  }
+  const int ublocks = (int)ceil_div(n_mu, 4);
+  for (int t = 0; t < max_iter; ++t) {
+    hipLaunchKernelGGL(km_assign, dim3(nparts), dim3(ASSIGN_THREADS), 0, st, P.a, G, n_mu, t, near_tie_rel);
+    hipLaunchKernelGGL(km_update, dim3(ublocks), dim3(256), 0, st, P.a, G, n_mu, t, nparts);
+  }
+  hipLaunchKernelGGL(km_assign, dim3(nparts), dim3(ASSIGN_THREADS), 0, st, P.a, G, n_mu, max_iter,
+                     near_tie_rel);
+  hipLaunchKernelGGL(km_snap, dim3(ublocks), dim3(256), 0, st, P.a, G, n_mu, idx);
+  hipLaunchKernelGGL(km_final, dim3(1), dim3(64), 0, st, P.a, nparts, info, objective, max_iter);
+  if (!launch_ok()) return ISDF_E_HIP;
+  return ISDF_OK;
+}

@@ -1,0 +1,116 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/isdf.h, and rejects bad arguments on the host before
+enqueueing anything."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2208_07731_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "isdf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(isdf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for n in ("isdf_kmeans", "isdf_fit", "isdf_fit_backward", "isdf_kmeans_workspace", "isdf_fit_workspace",
+              "isdf_fit_backward_workspace", "isdf_fit_minv_elems", "isdf_version", "isdf_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for n in header_functions():
+        assert hasattr(lib, n), n
+        assert n in L.SIGNATURES, n
+
+
+def test_strerror_and_version():
+    lib = L.load()
+    assert b"gfx950" in lib.isdf_version()
+    for code in (L.OK, L.E_ARG, L.E_WORKSPACE, L.E_HIP, L.E_UNSUPPORTED, L.E_NOT_PD, L.E_NONFINITE,
+                 L.W_EMPTY_CLUSTER, L.E_BAD_IDX):
+        assert L.strerror(code) != "unknown status"
+    assert L.strerror(12345) == "unknown status"
+
+
+def test_workspace_queries():
+    lib = L.load()
+    g = L.make_grid(24)
+    a = lib.isdf_kmeans_workspace(C.byref(g), 256, 30)
+    b = lib.isdf_kmeans_workspace(C.byref(g), 256, 60)
+    assert 0 < a < b
+    assert lib.isdf_kmeans_workspace(C.byref(g), 0, 30) == 0
+    f1 = lib.isdf_fit_workspace(C.byref(g), 256, 32, 32, 1, 0, 1000)
+    f2 = lib.isdf_fit_workspace(C.byref(g), 256, 32, 32, 1, 0, 2000)
+    assert 0 < f1 < f2
+    assert lib.isdf_fit_minv_elems(256, 1) == 256 * 256
+    assert lib.isdf_fit_minv_elems(256, 0) == 512 * 512
+    assert lib.isdf_fit_backward_workspace(C.byref(g), 256, 32, 32, 1, 0, 1000) > 0
+
+
+FAKE = 0x1000  # never dereferenced: every call below must fail its host checks
+
+
+@pytest.mark.parametrize("case", ["n_mu0", "n_mu_big", "null_c0", "neg_iter", "bad_ld", "bad_kind", "flags",
+                                  "no_ws", "bad_grid"])
+def test_kmeans_rejects_bad_arguments(case):
+    lib = L.load()
+    g = L.make_grid(8)
+    kw = dict(dt=L.C128, phi=FAKE, ld=4, n=4, kind=0, flags=0, n_mu=5, c0=FAKE, iters=3, idx=FAKE, info=FAKE,
+              ws=FAKE, wsb=1 << 30)
+    if case == "n_mu0":
+        kw["n_mu"] = 0
+    elif case == "n_mu_big":
+        kw["n_mu"] = 513
+    elif case == "null_c0":
+        kw["c0"] = None
+    elif case == "neg_iter":
+        kw["iters"] = -1
+    elif case == "bad_ld":
+        kw["ld"] = 3
+    elif case == "bad_kind":
+        kw["kind"] = 9
+    elif case == "flags":
+        kw["flags"] = 6
+    elif case == "no_ws":
+        kw["wsb"] = 16
+    elif case == "bad_grid":
+        g.n[1] = 0
+    code = lib.isdf_kmeans(C.byref(g), kw["dt"], kw["phi"], kw["ld"], kw["n"], kw["phi"], kw["ld"], kw["n"],
+                           kw["kind"], kw["flags"], kw["n_mu"], kw["c0"], kw["iters"], 1e-6, kw["idx"], None, None,
+                           None, None, kw["info"], kw["ws"], kw["wsb"], None)
+    assert code == (L.E_WORKSPACE if case == "no_ws" else L.E_ARG)
+
+
+@pytest.mark.parametrize("case", ["rows", "ld_theta", "prec_dtype", "null_minv", "flags", "no_ws", "unsupported"])
+def test_fit_rejects_bad_arguments(case):
+    lib = L.load()
+    g = L.make_grid(8)
+    kw = dict(dt=L.C128, prec=0, minv=FAKE, flags=1, row0=0, nrows=512, ldt=5, wsb=1 << 30)
+    if case == "rows":
+        kw["row0"] = 10
+    elif case == "ld_theta":
+        kw["ldt"] = 4
+    elif case == "prec_dtype":
+        kw["dt"] = L.C64
+    elif case == "null_minv":
+        kw["minv"] = None
+    elif case == "flags":
+        kw["flags"] = 2
+    elif case == "no_ws":
+        kw["wsb"] = 16
+    elif case == "unsupported":
+        kw["prec"] = 3
+        kw["dt"] = L.C64
+    code = lib.isdf_fit(C.byref(g), kw["dt"], FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, kw["prec"], kw["minv"], kw["flags"],
+                        kw["row0"], kw["nrows"], FAKE, kw["ldt"], 512, FAKE, FAKE, kw["wsb"], None)
+    expect = {"no_ws": L.E_WORKSPACE, "unsupported": L.E_UNSUPPORTED}.get(case, L.E_ARG)
+    assert code == expect

@@ -1,0 +1,152 @@
+"""GPU parity of isdf_fit (Gram + Hadamard on MFMA, FP64 Cholesky / inverse,
+Theta) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+isdf = pytest.importorskip("paper_2208_07731_amd")
+
+EPS = np.finfo(np.float64).eps
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def water8_fit(water8):
+    phi = water8["phi"]
+    wl = water8["wl"]
+    w = oracle.weight(phi, phi)
+    idx = oracle.kmeans(wl.n, w, water8["c0"], wl.kmeans_iters)["idx"]
+    ref = oracle.fit(phi, phi, idx)
+    kappa = oracle.cc_condition(phi, phi, idx)
+    return dict(phi=phi, idx=idx, ref=ref, kappa=kappa, wl=wl)
+
+
+def fp64_tol(kappa):
+    """Rounding-order differences in G and in the factorisation of C C^H move
+    Theta by about kappa * eps relative; 1e-12 is the target, kappa * eps the
+    floor below which no two FP64 orderings can be compared."""
+    return max(1e-12, 4.0 * kappa * EPS)
+
+
+def test_fit_fp64_water8(water8_fit):
+    f = water8_fit
+    theta, minv, info = isdf.fit(dev(f["phi"]), None, dev(f["idx"].astype(np.int32)))
+    th = theta.cpu().numpy()
+    assert th.dtype == np.float64
+    assert rel(th, f["ref"]["theta"].real) <= fp64_tol(f["kappa"])
+    assert info["status"] == 0 and info["pivot"] == -1
+    # minv against the oracle's inverse of C C^H
+    M = f["ref"]["M"].real
+    W = minv.cpu().numpy().reshape(M.shape)
+    assert rel(W @ M, np.eye(M.shape[0])) <= 1e2 * f["kappa"] * EPS
+    # interpolation property Theta(r_mu) = I
+    assert np.max(np.abs(th[f["idx"]] - np.eye(len(f["idx"])))) <= 10 * f["kappa"] * EPS
+    # pivots of the factorisation bound the spectrum of C C^H
+    ev = np.linalg.eigvalsh(M)
+    assert ev[0] * (1 - 1e-8) <= info["pivot_min"] and info["pivot_max"] <= ev[-1] * (1 + 1e-8)
+
+
+def test_fit_rblocks_bitwise(water8_fit):
+    """Rows are independent given minv: any partition of the rows into calls
+    and internal r-blocks gives bitwise equal Theta."""
+    f = water8_fit
+    phi, idx = dev(f["phi"]), dev(f["idx"].astype(np.int32))
+    full, minv, _ = isdf.fit(phi, None, idx)
+    a, _, _ = isdf.fit(phi, None, idx, minv=minv, factor=False, row0=0, nrows=5000, rblock=1234)
+    b, _, _ = isdf.fit(phi, None, idx, minv=minv, factor=False, row0=5000, nrows=full.shape[0] - 5000, rblock=777)
+    assert torch.equal(torch.cat([a, b]), full)
+
+
+def tiny_complex(seed, n=(5, 6, 7), n_phi=7, n_psi=9, n_mu=37, ld_pad=3):
+    rng = np.random.default_rng(seed)
+    nr = n[0] * n[1] * n[2]
+    big = rng.standard_normal((nr, n_phi + n_psi + ld_pad)) + 1j * rng.standard_normal((nr, n_phi + n_psi + ld_pad))
+    idx = rng.choice(nr, n_mu, replace=False).astype(np.int32)
+    return big, idx
+
+
+def test_fit_fp64_complex_ragged():
+    """Psi != Phi, strided operands (shared storage), odd orbital counts, N_r
+    and N_mu ragged against the 128-row / 16-column tiles."""
+    big, idx = tiny_complex(5)
+    t = dev(big)
+    phi_t, psi_t = t[:, :7], t[:, 7:16]
+    theta, _, info = isdf.fit(phi_t, psi_t, dev(idx), grid=(5, 6, 7))
+    ref = oracle.fit(big[:, :7], big[:, 7:16], idx)
+    kappa = oracle.cc_condition(big[:, :7], big[:, 7:16], idx)
+    th = theta.cpu().numpy()
+    assert th.dtype == np.complex128
+    assert rel(th, ref["theta"]) <= fp64_tol(kappa)
+
+
+def test_fit_fp64_complex_swap_conjugates():
+    big, idx = tiny_complex(6)
+    t = dev(big)
+    a, _, _ = isdf.fit(t[:, :7], t[:, 7:16], dev(idx), grid=(5, 6, 7))
+    b, _, _ = isdf.fit(t[:, 7:16], t[:, :7], dev(idx), grid=(5, 6, 7))
+    assert rel(b.cpu().numpy(), a.cpu().numpy().conj()) <= 1e-11
+
+
+def test_fit_sio2_shape_sampled_rows():
+    """SiO2-like workload (72^3 grid, N_phi = 192, N_psi = 384, N_mu = 3072,
+    complex): sampled rows of Theta against the oracle."""
+    d = synth.make_workload("sio2")
+    wl = d["wl"]
+    rng = np.random.default_rng(30)
+    idx = synth.init_centroids(d["env"] ** 2, wl.n, wl.n_mu, 3030)
+    idx = ((idx[:, 0] * wl.n + idx[:, 1]) * wl.n + idx[:, 2]).astype(np.int32)
+    psi_t = dev(d["psi"])
+    phi_t = psi_t[:, : wl.n_phi]
+    theta, _, info = isdf.fit(phi_t, psi_t, dev(idx), rblock=65536)
+    rows = np.sort(rng.choice(wl.n_r, 256, replace=False))
+    ref = oracle.fit(d["phi"], d["psi"], idx, rows=rows)
+    kappa = oracle.cc_condition(d["phi"], d["psi"], idx)
+    assert rel(theta[torch.as_tensor(rows).cuda()].cpu().numpy(), ref["theta"]) <= fp64_tol(kappa)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fit_fp32_gram_water8(water8_fit, dtype):
+    """FP32 MFMA Gram blocks, FP64 solve: error against the FP64 oracle on the
+    c128 data (and, for c64 storage, on the c64 data upcast)."""
+    f = water8_fit
+    phi = f["phi"] if dtype == "c128" else f["phi"].astype(np.complex64)
+    theta, _, info = isdf.fit(dev(phi), None, dev(f["idx"].astype(np.int32)), prec="fp32")
+    th = theta.cpu().numpy().astype(np.float64)
+    ref = f["ref"]["theta"].real if dtype == "c128" else \
+        oracle.fit_theta(phi.astype(np.complex128), phi.astype(np.complex128), f["idx"]).real
+    assert rel(th, ref) <= 1e-5
+
+
+def test_fit_duplicate_and_out_of_range_idx():
+    big, idx = tiny_complex(7)
+    t = dev(big)
+    bad = idx.copy()
+    bad[3] = bad[1]
+    _, _, info = isdf.fit(t[:, :7], t[:, 7:16], dev(bad), grid=(5, 6, 7), check=False)
+    assert info["status"] == 4 and info["bad_idx"] == 3
+    bad = idx.copy()
+    bad[2] = 10 ** 6
+    _, _, info = isdf.fit(t[:, :7], t[:, 7:16], dev(bad), grid=(5, 6, 7), check=False)
+    assert info["status"] == 4 and info["bad_idx"] == 2
+
+
+def test_fit_not_positive_definite():
+    """Orbitals vanishing at an interpolation point make C C^H exactly
+    singular: reported as not positive definite, with the pivot."""
+    big, idx = tiny_complex(8)
+    big[idx[0], :] = 0.0
+    t = dev(big)
+    _, _, info = isdf.fit(t[:, :7], None, dev(idx), grid=(5, 6, 7), check=False)
+    assert info["status"] == 1 and info["pivot"] == 0
