@@ -51,7 +51,9 @@ def _read_struct(buf: torch.Tensor, cls):
     return cls.from_buffer_copy(raw)
 
 
-def _grid(grid, n_r: int, h):
+def _grid(grid, n_r: int, h, geometry: bool = True):
+    if grid is None and not geometry:
+        grid = (n_r, 1, 1)  # the fit uses only the number of grid rows
     if grid is None:
         n = round(n_r ** (1.0 / 3.0))
         if n ** 3 != n_r:
@@ -156,9 +158,9 @@ def fit(phi: torch.Tensor, psi: torch.Tensor | None, idx: torch.Tensor, *, prec:
     lib = L.load()
     psi, dt, pp, lp, npf, ps, lps, nps, aliased = _fit_common(phi, psi, idx)
     n_r, n_mu = phi.shape[0], idx.numel()
-    g = _grid(grid, n_r, (1.0, 1.0, 1.0))
+    g = _grid(grid, n_r, (1.0, 1.0, 1.0), geometry=False)
     nrows = n_r - row0 if nrows is None else nrows
-    rblock = max(1, nrows) if rblock is None else rblock
+    rblock = max(1, min(nrows, 1 << 17)) if rblock is None else rblock
     p = _prec(prec)
     dev = phi.device
     n_minv = lib.isdf_fit_minv_elems(n_mu, int(aliased))
@@ -195,8 +197,8 @@ def fit_backward(phi: torch.Tensor, psi: torch.Tensor | None, idx: torch.Tensor,
     lib = L.load()
     psi, dt, pp, lp, npf, ps, lps, nps, aliased = _fit_common(phi, psi, idx)
     n_r, n_mu = phi.shape[0], idx.numel()
-    gr = _grid(grid, n_r, (1.0, 1.0, 1.0))
-    rblock = n_r if rblock is None else rblock
+    gr = _grid(grid, n_r, (1.0, 1.0, 1.0), geometry=False)
+    rblock = min(n_r, 1 << 17) if rblock is None else rblock
     p = _prec(prec)
     dev = phi.device
     if (theta_bar is None) == (g is None):

@@ -52,24 +52,6 @@ static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   return P;
 }
 
-static bool fit_args_ok(const isdf_grid* g, isdf_dtype dt, const void* phi, int64_t ld_phi, int n_phi,
-                        const void* psi, int64_t ld_psi, int n_psi, const int32_t* idx, int n_mu, isdf_prec prec,
-                        int64_t* nr_out) {
-  if (!g) return false;
-  for (int a = 0; a < 3; ++a)
-    if (g->n[a] <= 0) return false;
-  const int64_t nr = (int64_t)g->n[0] * g->n[1] * g->n[2];
-  if (nr >= INT32_MAX) return false;
-  if (dt != ISDF_C128 && dt != ISDF_C64) return false;
-  if (!phi || !psi || !idx || n_phi <= 0 || n_psi <= 0 || ld_phi < n_phi || ld_psi < n_psi) return false;
-  if (n_mu <= 0 || n_mu > nr) return false;
-  if (prec < ISDF_P_FP64 || prec > ISDF_P_FP16X3) return false;
-  *nr_out = nr;
-  return true;
-}
-
-static size_t tsize_of(isdf_prec p) { return p == ISDF_P_FP64 ? sizeof(double) : sizeof(float); }
-
 template <class T, class TS, class TT>
 static int fit_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                    bool aliased, const int32_t* idx, int n_mu, double* minv, uint32_t flags, int64_t row0,

@@ -1,0 +1,177 @@
+"""GPU parity of isdf_fit_backward (hand-written adjoint of the fit) against
+the FP64 oracle's adjoint, against central finite differences of the GPU
+forward, and through the torch.autograd wrappers."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+isdf = pytest.importorskip("paper_2208_07731_amd")
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def water8_idx(water8):
+    phi = water8["phi"]
+    wl = water8["wl"]
+    idx = oracle.kmeans(wl.n, oracle.weight(phi, phi), water8["c0"], wl.kmeans_iters)["idx"]
+    return idx
+
+
+def test_backward_fused_loss_aliased_water8(water8, water8_idx):
+    phi = water8["phi"]
+    g = synth.loss_field(phi.shape[0], 1004)
+    ref = oracle.fit_backward(phi, phi, water8_idx, g=g)
+    kappa = oracle.cc_condition(phi, phi, water8_idx)
+    phi_t, idx_t = dev(phi), dev(water8_idx.astype(np.int32))
+    _, minv, _ = isdf.fit(phi_t, None, idx_t, nrows=0)
+    dphi, dpsi, loss, info = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(g))
+    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    assert abs(loss.item() - ref["loss"]) <= tol * ref["loss"]
+    assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
+    assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
+    assert info["status"] == 0
+
+
+def tiny(seed, n=(5, 6, 7), n_phi=7, n_psi=9, n_mu=37):
+    rng = np.random.default_rng(seed)
+    nr = n[0] * n[1] * n[2]
+    big = rng.standard_normal((nr, n_phi + n_psi + 4)) + 1j * rng.standard_normal((nr, n_phi + n_psi + 4))
+    idx = rng.choice(nr, n_mu, replace=False).astype(np.int32)
+    return rng, big, idx
+
+
+@pytest.mark.parametrize("rblock", [None, 64])
+def test_backward_general_upstream_complex(rblock):
+    """Psi != Phi, strided operands, a random complex upstream gradient, one
+    r-block or several."""
+    rng, big, idx = tiny(11)
+    phi, psi = big[:, :7], big[:, 7:16]
+    tbar = rng.standard_normal((phi.shape[0], 37)) + 1j * rng.standard_normal((phi.shape[0], 37))
+    ref = oracle.fit_backward(phi, psi, idx, theta_bar=tbar)
+    t = dev(big)
+    _, minv, _ = isdf.fit(t[:, :7], t[:, 7:16], dev(idx), grid=(5, 6, 7), nrows=0)
+    dphi, dpsi, _, _ = isdf.fit_backward(t[:, :7], t[:, 7:16], dev(idx), minv, theta_bar=dev(tbar), grid=(5, 6, 7),
+                                         rblock=rblock)
+    kappa = oracle.cc_condition(phi, psi, idx)
+    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
+    assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
+
+
+def test_backward_fused_complex_multi_block():
+    rng, big, idx = tiny(12)
+    phi, psi = big[:, :7], big[:, 7:16]
+    g = rng.uniform(0.5, 1.5, phi.shape[0])
+    ref = oracle.fit_backward(phi, psi, idx, g=g)
+    t = dev(big)
+    _, minv, _ = isdf.fit(t[:, :7], t[:, 7:16], dev(idx), grid=(5, 6, 7), nrows=0)
+    dphi, dpsi, loss, _ = isdf.fit_backward(t[:, :7], t[:, 7:16], dev(idx), minv, g=dev(g), grid=(5, 6, 7),
+                                            rblock=50)
+    kappa = oracle.cc_condition(phi, psi, idx)
+    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    assert abs(loss.item() - ref["loss"]) <= tol * ref["loss"]
+    assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
+    assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
+
+
+def test_backward_aliased_general_upstream_real():
+    rng, big, idx = tiny(13, n_mu=20)
+    phi = big[:, :6]
+    tbar = rng.standard_normal((phi.shape[0], 20))
+    ref = oracle.fit_backward(phi, phi, idx, theta_bar=tbar)
+    t = dev(phi)
+    _, minv, _ = isdf.fit(t, None, dev(idx), grid=(5, 6, 7), nrows=0)
+    dphi, dpsi, _, _ = isdf.fit_backward(t, None, dev(idx), minv, theta_bar=dev(tbar), grid=(5, 6, 7), rblock=100)
+    kappa = oracle.cc_condition(phi, phi, idx)
+    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
+    assert torch.equal(dphi, dpsi)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_backward_fp32_gram_water8(water8, water8_idx, dtype):
+    """FP32 Gram and adjoint contractions, FP64 solves: gradient error against
+    the FP64 oracle (c64 storage: against the oracle on the upcast data)."""
+    phi = water8["phi"] if dtype == "c128" else water8["phi"].astype(np.complex64)
+    phi64 = phi.astype(np.complex128)
+    g = synth.loss_field(phi.shape[0], 1004)
+    ref = oracle.fit_backward(phi64, phi64, water8_idx, g=g)
+    phi_t, idx_t = dev(phi), dev(water8_idx.astype(np.int32))
+    _, minv, _ = isdf.fit(phi_t, None, idx_t, prec="fp32", nrows=0)
+    dphi, _, loss, _ = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(g), prec="fp32")
+    assert rel(dphi.cpu().numpy().astype(np.complex128), ref["dphi"]) <= 1e-4
+    assert abs(loss.item() - ref["loss"]) <= 1e-5 * ref["loss"]
+
+
+def test_autograd_fit_matches_oracle():
+    rng, big, idx = tiny(14)
+    phi_t = dev(big[:, :7]).requires_grad_()
+    psi_t = dev(big[:, 7:16]).requires_grad_()
+    th = isdf.ISDFFit.apply(phi_t, psi_t, dev(idx))
+    tbar = rng.standard_normal(th.shape) + 1j * rng.standard_normal(th.shape)
+    (torch.real(torch.sum(dev(tbar).conj() * th))).backward()
+    ref = oracle.fit_backward(big[:, :7], big[:, 7:16], idx, theta_bar=tbar)
+    assert rel(phi_t.grad.cpu().numpy(), ref["dphi"]) <= 1e-9
+    assert rel(psi_t.grad.cpu().numpy(), ref["dpsi"]) <= 1e-9
+
+
+def test_autograd_loss_aliased_accumulates_both_arguments(water8, water8_idx):
+    phi = water8["phi"]
+    g = synth.loss_field(phi.shape[0], 1004)
+    phi_t = dev(phi).requires_grad_()
+    L = isdf.ISDFLoss.apply(phi_t, phi_t, dev(water8_idx.astype(np.int32)), dev(g))
+    L.backward()
+    ref = oracle.fit_backward(phi, phi, water8_idx, g=g)
+    assert abs(L.item() - ref["loss"]) <= 1e-10 * ref["loss"]
+    assert rel(phi_t.grad.cpu().numpy(), ref["dphi"] + ref["dpsi"]) <= 1e-9
+
+
+def test_backward_water64_central_fd():
+    """Adjoint workload (64^3 grid, N_e = 256, N_mu = 2048, Psi holding Phi's
+    values): fused-loss gradients against central differences (h = 1e-6) of
+    the GPU forward on 20 random entries of each orbital set, real and
+    imaginary parts."""
+    d = synth.make_workload("water64_adj")
+    wl = d["wl"]
+    phi = d["phi"]
+    g = d["g"]
+    rng = np.random.default_rng(1000 * wl.cfg + 5)
+    idx = synth.init_centroids(d["env"] ** 2, wl.n, wl.n_mu, 1000 * wl.cfg + 3)
+    idx = ((idx[:, 0] * wl.n + idx[:, 1]) * wl.n + idx[:, 2]).astype(np.int32)
+    phi_t, idx_t, g_t = dev(phi), dev(idx), dev(g)
+    _, minv, _ = isdf.fit(phi_t, None, idx_t, nrows=0)
+    dphi, dpsi, loss, _ = isdf.fit_backward(phi_t, None, idx_t, minv, g=g_t)
+    dphi = dphi.cpu().numpy()
+    scale = np.max(np.abs(dphi))
+    h = 1e-6
+
+    def L(p, s):
+        th, _, _ = isdf.fit(p, s, idx_t)
+        return float(torch.sum(g_t[:, None] * torch.abs(th) ** 2).item())
+
+    errs = []
+    for which in ("phi", "psi"):
+        for _ in range(20):
+            r, c = int(rng.integers(wl.n_r)), int(rng.integers(wl.n_phi))
+            for unit in (1.0, 1j):
+                vals = []
+                for sgn in (1.0, -1.0):
+                    x = phi_t.clone()
+                    x[r, c] += sgn * unit * h
+                    vals.append(L(x, phi_t) if which == "phi" else L(phi_t, x))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                an = dphi[r, c].real if unit == 1.0 else dphi[r, c].imag
+                errs.append(abs(fd - an) / scale)
+    assert max(errs) <= 1e-6, max(errs)
