@@ -1,0 +1,208 @@
+#!/usr/bin/env python
+"""ISDF benchmark on one MI355X: K-means + fit + adjoint of the 64-water workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload water64]
+                    [--prec fp64] [--mixed fp32] [--no-cpu-baseline]
+
+One step = the whole hot path on inputs resident in HBM: SSM weight and
+K-means (up to the workload's round count), factorisation and inverse of
+C C^H, Z C^H, Theta = Z C^H (C C^H)^-1, and the adjoint with the fused loss
+L = sum_r g_r sum_mu |Theta_r,mu|^2.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, MI355X dense MFMA
+HBM_PEAK = 8000.0  # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gemm.h", "fitlib.h", "fit.hip"):
+        with open(os.path.join(ROOT, "paper_2208_07731_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM traffic of the solve GEMM from the committed PMC summary, only if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"pmc_dgemm_apply_minv_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(d, idx, iters_run: int) -> dict:
+    """The FP64 oracle on a bounded sample of the same workload, scaled to
+    one full step (ms): weight at full size, two K-means rounds at full size
+    (scaled to the rounds the GPU ran), and the fit and fused-loss adjoint on
+    two sub-problems made of the interpolation rows plus 1024 / 3072 other
+    grid rows, whose per-row slope is scaled to N_r."""
+    import numpy as np
+
+    import oracle
+
+    wl = d["wl"]
+    phi, g = d["phi"], d["g"]
+    t0 = time.perf_counter()
+    w = oracle.weight(phi, None)
+    t_w = time.perf_counter() - t0
+    pts = oracle.grid_points(wl.n)
+    s = oracle.metric_scale()
+    t0 = time.perf_counter()
+    c = d["c0"]
+    for _ in range(2):
+        lab, _, _ = oracle.assign(pts, c, s)
+        c, _ = oracle.update(pts, w, lab, c)
+    t_round = (time.perf_counter() - t0) / 2
+    rng = np.random.default_rng(7)
+    others = np.setdiff1d(np.arange(wl.n_r), idx)
+    t_fit, t_bwd = [], []
+    sizes = (1024, 3072)
+    for extra in sizes:
+        rows = np.concatenate([idx, rng.choice(others, extra, replace=False)])
+        sub = np.ascontiguousarray(phi[rows])
+        loc = np.arange(len(idx))
+        t0 = time.perf_counter()
+        oracle.fit(sub, sub, loc)
+        t_fit.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        oracle.fit_backward(sub, sub, loc, g=g[rows])
+        t_bwd.append(time.perf_counter() - t0)
+    slope_f = (t_fit[1] - t_fit[0]) / (sizes[1] - sizes[0])
+    slope_b = (t_bwd[1] - t_bwd[0]) / (sizes[1] - sizes[0])
+    fix_f = t_fit[0] - slope_f * (len(idx) + sizes[0])
+    fix_b = t_bwd[0] - slope_b * (len(idx) + sizes[0])
+    total = t_w + t_round * (iters_run + 1) + (fix_f + slope_f * wl.n_r) + (fix_b + slope_b * wl.n_r)
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": round(total * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+        "sample": (f"numpy/scipy FP64 oracle on {cores} host threads: weight at full size, 2 of "
+                   f"{iters_run + 1} K-means rounds at full size, fit and fused adjoint on sub-problems of "
+                   f"N_mu+1024 and N_mu+3072 grid rows, extrapolated linearly in rows and rounds"),
+        "phases_s": {"weight": round(t_w, 3), "kmeans_round": round(t_round, 3),
+                     "fit_rows_slope_us": round(slope_f * 1e6, 2), "bwd_rows_slope_us": round(slope_b * 1e6, 2)},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="water64")
+    ap.add_argument("--prec", default="fp64")
+    ap.add_argument("--mixed", default="fp32", help="second Gram precision to time ('' to skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the ISDF path here has no "
+              f"multi-GPU mode.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2208_07731_amd.pipeline import ISDFStep
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    d = synth.make_workload(args.workload)
+    wl = d["wl"]
+    log(f"[bench] workload {wl.name}: N_r={wl.n_r} N_e={wl.n_phi} N_mu={wl.n_mu} ({time.time() - t0:.1f}s)")
+    phi = torch.as_tensor(d["phi"]).cuda()
+    psi = phi if wl.aliased else torch.as_tensor(d["psi"]).cuda()
+    if not wl.aliased:
+        phi = psi[:, : wl.n_phi]
+    g = torch.as_tensor(d["g"]).cuda()
+    torch.cuda.synchronize()
+
+    def run(prec, steps, warmup):
+        st = ISDFStep(phi, None if wl.aliased else psi, wl.n_mu, d["c0"], wl.kmeans_iters, g=g, prec=prec)
+        for _ in range(warmup):
+            st.enqueue()
+        info = st.check()
+        ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+        solve = [(ev(), ev()) for _ in range(steps)]
+        phases = [[ev() for _ in range(6)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        start, stop = ev(), ev()
+        start.record()
+        for k in range(steps):
+            st.enqueue(solve_events=solve[k], phase_events=phases[k])
+        stop.record()
+        torch.cuda.synchronize()
+        info = st.check()
+        total = start.elapsed_time(stop) / steps
+        solve_ms = sum(a.elapsed_time(b) for a, b in solve) / steps
+        names = ["kmeans", "factor", "zc", "solve", "adjoint"]
+        ph = {n: round(sum(p[i].elapsed_time(p[i + 1]) for p in phases) / steps, 3) for i, n in enumerate(names)}
+        return st, total, solve_ms, ph, info
+
+    log(f"[bench] {args.prec}: warmup {args.warmup}, timing {args.steps} steps")
+    st, ms, solve_ms, phases, info = run(args.prec, args.steps, args.warmup)
+    log(f"[bench] {args.prec}: {ms:.2f} ms/step, phases {phases}")
+    n1 = wl.n_mu if wl.aliased else 2 * wl.n_mu
+    flops = 2.0 * wl.n_r * n1 * n1
+    achieved = flops / (solve_ms * 1e-3) / 1e12
+    traffic = read_traffic(wl.name)
+    out = {
+        "metric": "ISDF time (K-means+fit+bwd), % MFMA/HBM peak, mixed vs FP64 at 1e-6 rel err",
+        "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else args.prec, "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.n}^3 grid (N_r={wl.n_r}), N_e={wl.n_phi}, N_mu={wl.n_mu}, "
+                               f"{'Phi=Psi' if wl.aliased else 'Phi!=Psi'}, K-means {wl.kmeans_iters} rounds, "
+                               f"fit + fused-loss adjoint", "gram_prec": args.prec},
+        "phases_ms": phases,
+        "kmeans": {"rounds": info["kmeans"]["iters"], "converged": info["kmeans"]["converged"]},
+        "roofline": {"bound": "mfma", "kernel": "FP64 GEMM Theta = (Z C^H)(C C^H)^-1",
+                     "achieved": round(achieved, 2), "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["fp64"], 4), "traffic": traffic,
+                     "flops_per_launch": flops, "ms_per_launch": round(solve_ms, 3)},
+    }
+    if args.mixed:
+        theta64 = st.theta.clone()
+        del st
+        torch.cuda.empty_cache()
+        log(f"[bench] {args.mixed}: timing")
+        st2, ms2, _, ph2, _ = run(args.mixed, args.steps, args.warmup)
+        err = float(torch.linalg.norm(st2.theta.double() - theta64) / torch.linalg.norm(theta64))
+        out["mixed"] = {"gram_prec": args.mixed, "ms_per_step": round(ms2, 3), "phases_ms": ph2,
+                        "theta_rel_err_vs_fp64_gpu": err, "speedup": round(ms / ms2, 3)}
+        del st2, theta64
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle on a bounded sample)")
+        c0 = np.asarray(d["c0"], dtype=np.int64)  # seeds are distinct grid points
+        idx = (c0[:, 0] * wl.n + c0[:, 1]) * wl.n + c0[:, 2]
+        out["cpu_baseline"] = cpu_baseline(d, idx, out["kmeans"]["rounds"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

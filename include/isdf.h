@@ -187,6 +187,33 @@ int isdf_fit(const isdf_grid* grid /* host */, isdf_dtype dt,
              isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The two halves of isdf_fit, as separate calls for callers that stream or
+ * reuse Z C^H:
+ *
+ * isdf_zc: rows [row0, row0 + nrows) of Z C^H = A .* conj(B) (eq. muRownuCol
+ * with eq. muRownuColden), Z never formed.  G is [nrows][ldg] FP64: real
+ * (aliased, ldg >= n_mu) or interleaved complex (ldg >= 2 n_mu doubles).
+ * Workspace: isdf_zc_workspace bytes.
+ */
+size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec);
+int isdf_zc(const isdf_grid* grid /* host */, isdf_dtype dt,
+            const void* phi, int64_t ld_phi, int32_t n_phi,
+            const void* psi, int64_t ld_psi, int32_t n_psi,
+            const int32_t* idx, int32_t n_mu, isdf_prec prec,
+            int64_t row0, int64_t nrows, double* G, int64_t ldg,
+            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * isdf_apply_minv: Theta = G (C C^H)^-1 for `nrows` rows (the solve of
+ * eq. theta), minv as left by isdf_fit with ISDF_FIT_FACTOR, G as written by
+ * isdf_zc.  theta: [nrows][ld_theta], real (aliased) or interleaved complex,
+ * double (ISDF_C128) or float (ISDF_C64); ld_theta >= n_mu.  One FP64 GEMM
+ * launch; no workspace.
+ */
+int isdf_apply_minv(int32_t n_mu, int32_t aliased, const double* minv, const double* G, int64_t ldg,
+                    int64_t nrows, isdf_dtype dt, void* theta, int64_t ld_theta, void* stream);
+
+/*
  * Adjoint of isdf_fit with the interpolation points fixed (the paper gives
  * no adjoint; this is reverse-mode differentiation of eq. theta).  With
  * Theta = G M^-1, G = A .* conj(B), M = G[idx]:

@@ -138,3 +138,70 @@ extern "C" int isdf_fit(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
                                       aliased, idx, n_mu, minv, flags, row0, nrows, (float*)theta, ld_theta, rblock,
                                       info, P, s);
 }
+
+extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec) {
+  if (n_mu <= 0 || n_phi <= 0 || n_psi <= 0) return 0;
+  Carver c(nullptr, 0);
+  const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
+  c.take<int>(64);  // abort flag
+  c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize_of(prec));
+  if (!aliased) c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize_of(prec));
+  return c.used;
+}
+
+template <class T, class TS>
+static int zc_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                  bool aliased, const int32_t* idx, int n_mu, int64_t row0, int64_t nrows, double* G, int64_t ldg,
+                  void* ws, size_t cap, hipStream_t s) {
+  Carver c(ws, cap);
+  const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
+  int* ab = c.take<int>(64);
+  T* Ephi = c.take<T>((size_t)2 * nmu16 * 2 * n_phi);
+  T* Epsi = aliased ? Ephi : c.take<T>((size_t)2 * nmu16 * 2 * n_psi);
+  if (!c.fits() || !ws) return ISDF_E_WORKSPACE;
+  if (!fill<int>(ab, 1, 0, s)) return ISDF_E_HIP;
+  if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
+  if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
+  if (nrows > 0 && !gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr,
+                                row0, (int)nrows, G, ldg, aliased ? G_REAL : G_CPLX, ab, s))
+    return ISDF_E_HIP;
+  return ISDF_OK;
+}
+
+extern "C" int isdf_zc(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+                       const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
+                       isdf_prec prec, int64_t row0, int64_t nrows, double* G, int64_t ldg, void* ws,
+                       size_t ws_bytes, void* stream) {
+  int64_t nr = 0;
+  if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
+  const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
+  if (row0 < 0 || nrows < 0 || row0 + nrows > nr || nrows > INT32_MAX || (nrows > 0 && !G)) return ISDF_E_ARG;
+  if (ldg < (aliased ? n_mu : 2 * (int64_t)n_mu)) return ISDF_E_ARG;
+  if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
+  if (prec == ISDF_P_BF16X6 || prec == ISDF_P_FP16X3) return ISDF_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ISDF_P_FP64)
+    return zc_run<double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi, aliased,
+                                  idx, n_mu, row0, nrows, G, ldg, ws, ws_bytes, s);
+  if (dt == ISDF_C128)
+    return zc_run<float, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi, aliased,
+                                 idx, n_mu, row0, nrows, G, ldg, ws, ws_bytes, s);
+  return zc_run<float, float>(nr, (const float*)phi, ld_phi, n_phi, (const float*)psi, ld_psi, n_psi, aliased, idx,
+                              n_mu, row0, nrows, G, ldg, ws, ws_bytes, s);
+}
+
+extern "C" int isdf_apply_minv(int32_t n_mu, int32_t aliased, const double* minv, const double* G, int64_t ldg,
+                               int64_t nrows, isdf_dtype dt, void* theta, int64_t ld_theta, void* stream) {
+  const int64_t n1 = aliased ? n_mu : 2 * (int64_t)n_mu;
+  if (n_mu <= 0 || !minv || nrows < 0 || nrows > INT32_MAX || (nrows > 0 && (!G || !theta))) return ISDF_E_ARG;
+  if (ldg < n1 || ld_theta < n_mu || (dt != ISDF_C128 && dt != ISDF_C64)) return ISDF_E_ARG;
+  if (nrows == 0) return ISDF_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ldt = aliased ? ld_theta : 2 * ld_theta;
+  bool ok = dt == ISDF_C128
+                ? dgemm<KC, KC, double>((int)nrows, (int)n1, n1, G, ldg, minv, n1, (double*)theta, ldt, 1.0, 0.0, 0,
+                                        nullptr, s)
+                : dgemm<KC, KC, float>((int)nrows, (int)n1, n1, G, ldg, minv, n1, (float*)theta, ldt, 1.0, 0.0, 0,
+                                       nullptr, s);
+  return ok ? ISDF_OK : ISDF_E_HIP;
+}
