@@ -76,14 +76,8 @@ struct TileCfg {
   static constexpr int THREADS = WM * WN * ISDF_WAVE;
   static constexpr int WTM = BM / WM, WTN = BN / WN;  // wave tile
   static constexpr int MI = WTM / 16, NI = WTN / 16;  // MFMA tiles per wave
-  // LDS row padding: a row stride of (BM + 16) elements puts the four
-  // 16-lane groups of an MFMA operand read in alternating bank halves.
-  static constexpr int PAD = 16;
-  static constexpr int LDA = BM + PAD, LDB = BN + PAD;
-  static constexpr int A_ELEMS = BM * BK / THREADS;  // per-thread prefetch
-  static constexpr int B_ELEMS = BN * BK / THREADS;
   static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile");
-  static_assert(BK % 4 == 0, "bk");
+  static_assert(BK % 16 == 0, "bk");
   static_assert((BM * BK) % THREADS == 0 && (BN * BK) % THREADS == 0, "load split");
   // row (within a 16x16 MFMA tile) of accumulator element j of `lane`
   __device__ __forceinline__ static int orow(int lane, int j) {
@@ -91,53 +85,99 @@ struct TileCfg {
   }
 };
 
+// LDS image of one BK slice of an operand (X x BK elements of T):
+//   KC: [X][BK + PK] -- k contiguous, as loaded from a KC operand
+//   XC: [BK][X + PX] -- x contiguous, as loaded from an XC operand
+// Both are read with the same k order: in MFMA sub-step s of a 16-deep
+// chunk c, lane group q = lane / 16 supplies k = 16 c + 4 q + s for A and B
+// alike, so a KC lane reads four consecutive k with one vector load.
+template <class T, int LAYOUT, int X, int BK>
+struct Lds {
+  static constexpr int PK = 16 / (int)sizeof(T);  // 16-byte pad per row
+  static constexpr int PX = 16;
+  static constexpr int SIZE = LAYOUT == KC ? X * (BK + PK) : BK * (X + PX);
+  __device__ __forceinline__ static int at(int x, int k) {
+    return LAYOUT == KC ? x * (BK + PK) + k : k * (X + PX) + x;
+  }
+};
+
+template <class TS>
+__device__ __forceinline__ void load_pair(const TS* p, double& a, double& b);
+template <>
+__device__ __forceinline__ void load_pair<double>(const double* p, double& a, double& b) {
+  double2 v = *reinterpret_cast<const double2*>(p);
+  a = v.x;
+  b = v.y;
+}
+template <>
+__device__ __forceinline__ void load_pair<float>(const float* p, double& a, double& b) {
+  float2 v = *reinterpret_cast<const float2*>(p);
+  a = v.x;
+  b = v.y;
+}
+
 // Per-thread prefetch of one BK slice of an operand (X rows x BK), in the
 // compute type.  KC: thread -> (x, run of E consecutive k); XC: thread ->
-// (k, run of E consecutive x).
+// (k, run of E consecutive x).  Interior slices of aligned operands use
+// unguarded pair loads; edge slices guard every element.
 template <class T, class TS, int LAYOUT, int X, int BK, int THREADS>
 struct Stager {
   static constexpr int E = X * BK / THREADS;
+  static_assert(E % 2 == 0, "pairs");
   T v[E];
-  __device__ __forceinline__ void load(const Operand<TS>& op, int x0, int xlim, int64_t k0, int64_t klim,
-                                       int tid, int64_t rowcache) {
+  __device__ __forceinline__ void load(const Operand<TS>& op, int x0, int xlim, int64_t k0, int64_t klim, int tid,
+                                       int64_t rowcache, bool aligned) {
+    const bool interior = aligned && (x0 + X <= xlim) && (k0 + BK <= klim);
     if (LAYOUT == KC) {
       constexpr int RUNS = BK / E;  // threads per x
       const int x = tid / RUNS;
       const int64_t kb = k0 + (tid % RUNS) * E;
-      const bool okx = (x0 + x) < xlim;
-      const TS* base = op.p + rowcache * op.ld;
+      const TS* base = op.p + rowcache * op.ld + kb;
+      if (interior) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int64_t k = kb + e;
-        v[e] = (okx && k < klim) ? (T)base[k] : (T)0;
+        for (int e = 0; e < E; e += 2) {
+          double a, b;
+          load_pair<TS>(base + e, a, b);
+          v[e] = (T)a;
+          v[e + 1] = (T)b;
+        }
+      } else {
+        const bool okx = (x0 + x) < xlim;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = (okx && kb + e < klim) ? (T)base[e] : (T)0;
       }
     } else {
       constexpr int RUNS = X / E;  // threads per k
       const int64_t k = k0 + tid / RUNS;
       const int xb = x0 + (tid % RUNS) * E;
-      const bool okk = k < klim;
-      const TS* base = op.p + k * op.ld;
+      const TS* base = op.p + k * op.ld + xb;
+      if (interior) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int x = xb + e;
-        v[e] = (okk && x < xlim) ? (T)base[x] : (T)0;
+        for (int e = 0; e < E; e += 2) {
+          double a, b;
+          load_pair<TS>(base + e, a, b);
+          v[e] = (T)a;
+          v[e + 1] = (T)b;
+        }
+      } else {
+        const bool okk = k < klim;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = (okk && xb + e < xlim) ? (T)base[e] : (T)0;
       }
     }
   }
-  // LDS tile s[BK][X + pad]
-  __device__ __forceinline__ void store(T* s, int lds_ld, int tid) const {
+  __device__ __forceinline__ void store(T* s, int tid) const {
+    typedef Lds<T, LAYOUT, X, BK> L;
     if (LAYOUT == KC) {
       constexpr int RUNS = BK / E;
-      const int x = tid / RUNS;
-      const int kb = (tid % RUNS) * E;
+      T* d = s + L::at(tid / RUNS, (tid % RUNS) * E);
 #pragma unroll
-      for (int e = 0; e < E; ++e) s[(kb + e) * lds_ld + x] = v[e];
+      for (int e = 0; e < E; ++e) d[e] = v[e];
     } else {
       constexpr int RUNS = X / E;
-      const int k = tid / RUNS;
-      const int xb = (tid % RUNS) * E;
+      T* d = s + L::at((tid % RUNS) * E, tid / RUNS);
 #pragma unroll
-      for (int e = 0; e < E; ++e) s[k * lds_ld + xb + e] = v[e];
+      for (int e = 0; e < E; ++e) d[e] = v[e];
     }
   }
   // Global row of this thread's x (KC), resolved once per tile.
@@ -148,53 +188,86 @@ struct Stager {
     const int xc = x < xlim ? x : (xlim > 0 ? xlim - 1 : 0);
     return op.rows ? (int64_t)op.rows[xc] : (int64_t)xc;
   }
+  __device__ __forceinline__ static bool aligned(const Operand<TS>& op) {
+    return (op.ld % 2 == 0) && (((uintptr_t)op.p) % (2 * sizeof(TS)) == 0);
+  }
 };
 
-// Runs the K loop of one operand pair into acc.
+// Operand values of lane `lane` for the four sub-steps of chunk c: element
+// (x, 16 c + 4 (lane / 16) + s), s = 0..3.
+template <class T, int LAYOUT, int X, int BK>
+__device__ __forceinline__ void read4(const T* s, int x, int c, int lane, T (&o)[4]) {
+  typedef Lds<T, LAYOUT, X, BK> L;
+  const int k = 16 * c + 4 * (lane >> 4);
+  if (LAYOUT == KC) {
+    const T* p = s + L::at(x, k);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = p[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = s[L::at(x, k + j)];
+  }
+}
+
+// Runs the K loop of one operand pair into acc.  LDS is double buffered:
+// the slice for step i+1 is loaded from global memory while step i feeds the
+// MFMAs, stored into the other buffer, and one barrier per step separates
+// the two.
 template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK>
 __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
-                                         int N, int64_t kbeg, int64_t kend, T* As, T* Bs,
+                                         int N, int64_t kbeg, int64_t kend, T* smem,
                                          typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI]) {
+  typedef Lds<T, LA, BM, BK> LA_;
+  typedef Lds<T, LB, BN, BK> LB_;
+  constexpr int STAGE = LA_::SIZE + LB_::SIZE;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int wm = wv / (BN / Cfg::WTN);
   const int wn = wv % (BN / Cfg::WTN);
-  Stager<T, TA, LA, BM, BK, Cfg::THREADS> sa;
-  Stager<T, TB, LB, BN, BK, Cfg::THREADS> sb;
-  const int64_t rowa = Stager<T, TA, LA, BM, BK, Cfg::THREADS>::row_of(A, m0, M, tid);
-  const int64_t rowb = Stager<T, TB, LB, BN, BK, Cfg::THREADS>::row_of(B, n0, N, tid);
+  typedef Stager<T, TA, LA, BM, BK, Cfg::THREADS> SA;
+  typedef Stager<T, TB, LB, BN, BK, Cfg::THREADS> SB;
+  SA sa;
+  SB sb;
+  const int64_t rowa = SA::row_of(A, m0, M, tid);
+  const int64_t rowb = SB::row_of(B, n0, N, tid);
+  const bool ala = SA::aligned(A), alb = SB::aligned(B);
   if (kbeg >= kend) return;
-  sa.load(A, m0, M, kbeg, kend, tid, rowa);
-  sb.load(B, n0, N, kbeg, kend, tid, rowb);
-  sa.store(As, Cfg::LDA, tid);
-  sb.store(Bs, Cfg::LDB, tid);
+  sa.load(A, m0, M, kbeg, kend, tid, rowa, ala);
+  sb.load(B, n0, N, kbeg, kend, tid, rowb, alb);
+  sa.store(smem, tid);
+  sb.store(smem + LA_::SIZE, tid);
   __syncthreads();
+  int cur = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) {
-      sa.load(A, m0, M, k0 + BK, kend, tid, rowa);
-      sb.load(B, n0, N, k0 + BK, kend, tid, rowb);
+      sa.load(A, m0, M, k0 + BK, kend, tid, rowa, ala);
+      sb.load(B, n0, N, k0 + BK, kend, tid, rowb, alb);
     }
+    const T* As = smem + cur * STAGE;
+    const T* Bs = As + LA_::SIZE;
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T a[Cfg::MI], b[Cfg::NI];
-      const int kr = kk + (lane >> 4);
+    for (int c = 0; c < BK / 16; ++c) {
+      T a[Cfg::MI][4], b[Cfg::NI][4];
 #pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i) a[i] = As[kr * Cfg::LDA + wm * Cfg::WTM + i * 16 + (lane & 15)];
+      for (int i = 0; i < Cfg::MI; ++i) read4<T, LA, BM, BK>(As, wm * Cfg::WTM + i * 16 + (lane & 15), c, lane, a[i]);
 #pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j) b[j] = Bs[kr * Cfg::LDB + wn * Cfg::WTN + j * 16 + (lane & 15)];
+      for (int j = 0; j < Cfg::NI; ++j) read4<T, LB, BN, BK>(Bs, wn * Cfg::WTN + j * 16 + (lane & 15), c, lane, b[j]);
 #pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i)
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int j = 0; j < Cfg::NI; ++j) MfmaT<T>::mma(a[i], b[j], acc[i][j]);
+        for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+          for (int j = 0; j < Cfg::NI; ++j) MfmaT<T>::mma(a[i][s], b[j][s], acc[i][j]);
+    }
+    if (more) {
+      T* nxt = smem + (cur ^ 1) * STAGE;
+      sa.store(nxt, tid);
+      sb.store(nxt + LA_::SIZE, tid);
     }
     __syncthreads();
-    if (more) {
-      sa.store(As, Cfg::LDA, tid);
-      sb.store(Bs, Cfg::LDB, tid);
-      __syncthreads();
-    }
+    cur ^= 1;
   }
 }
 
@@ -209,13 +282,13 @@ struct TileAt {
 // accumulator sets, same tile, e.g. Phi and Psi Gram blocks).
 template <class T, int BM, int BN, int BK, int WM, int WN, class TA, int LA, class TB, int LB, int NOPS,
           class Epi>
-__global__ __launch_bounds__(WM* WN* ISDF_WAVE) void gemm_kernel(GemmShape sh, Operand<TA> A0, Operand<TB> B0,
+__global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh, Operand<TA> A0, Operand<TB> B0,
                                                                  Operand<TA> A1, Operand<TB> B1, int64_t K1,
                                                                  Epi epi) {
   typedef TileCfg<T, BM, BN, BK, WM, WN> Cfg;
   if (sh.abort && *sh.abort) return;
-  __shared__ T As[BK * Cfg::LDA];
-  __shared__ T Bs[BK * Cfg::LDB];
+  constexpr int STAGE = Lds<T, LA, BM, BK>::SIZE + Lds<T, LB, BN, BK>::SIZE;
+  __shared__ __attribute__((aligned(16))) T smem[2 * STAGE];
   const int tiles_n = (sh.N + BN - 1) / BN;
   const int tiles_m = (sh.M + BM - 1) / BM;
   const int logical = xcd_remap(blockIdx.x, tiles_m * tiles_n);
@@ -231,7 +304,7 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE) void gemm_kernel(GemmShape sh, O
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
     for (int j = 0; j < Cfg::NI; ++j) acc0[i][j] = typename MfmaT<T>::acc_t{0, 0, 0, 0};
-  mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK>(A0, B0, m0, n0, sh.M, sh.N, kbeg, kend, As, Bs, acc0);
+  mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK>(A0, B0, m0, n0, sh.M, sh.N, kbeg, kend, smem, acc0);
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -244,7 +317,7 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE) void gemm_kernel(GemmShape sh, O
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j) acc1[i][j] = typename MfmaT<T>::acc_t{0, 0, 0, 0};
     __syncthreads();
-    mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK>(A1, B1, m0, n0, sh.M, sh.N, 0, K1, As, Bs, acc1);
+    mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK>(A1, B1, m0, n0, sh.M, sh.N, 0, K1, smem, acc1);
     epi.template apply2<Cfg>(acc0, acc1, at);
   } else {
     epi.template apply<Cfg>(acc0, at);
