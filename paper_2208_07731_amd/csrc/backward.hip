@@ -7,13 +7,16 @@
 //   Abar = Gbar .* B,  Bbar = conj(Gbar) .* A,
 //   dPhi = Abar Phi_mu,  dPhi[idx] += Abar^H Phi,  (same for Psi with Bbar).
 //
-// Theta, G, A, B are recomputed one r-block at a time and never stored
-// whole.  Per block: Gram + Hadamard (A, B and G kept for the block), Theta
-// = G M^-1 and S = Thetabar M^-1 (FP64 GEMMs; with the fused loss
-// L = sum g |Theta|^2, Thetabar = 2 g Theta is folded into S as a row scale),
-// the split-K partials of Theta^T S and Abar^T Phi (reduced in a fixed
-// order, so the result is deterministic), Abar / Bbar in place, and the
-// block's rows of dPhi = Abar Phi_mu.  The Mbar terms touch only the N_mu
+// G, A, B are recomputed one r-block at a time and never stored whole.
+// General upstream Thetabar: per block Theta = G M^-1 and S = Thetabar M^-1
+// (FP64 GEMMs), the split-K partials of Theta^T S, Abar / Bbar in place.
+// Fused loss L = sum_r g_r sum_mu |Theta_r,mu|^2 (Thetabar = 2 g Theta):
+// S = 2 g . (G M^-2) and Theta^T S = 2 M^-1 H M^-2 with H = G^T diag(g) G,
+// so Theta is never formed: per block one FP64 GEMM G M^-2 whose epilogue
+// writes Abar / Bbar and the loss, and the lower half of H (split-K).
+// Either way the block's rows of dPhi = Abar Phi_mu and the partials of
+// Abar^T Phi follow; every split-K reduction runs in a fixed order, so the
+// result is deterministic.  The Mbar terms touch only the N_mu
 // interpolation rows and are applied once after the last block.
 #include "fitlib.h"
 
@@ -90,17 +93,25 @@ __global__ void reduce_splits(double* __restrict__ out, const double* __restrict
   }
 }
 
-// Theta store + per-workgroup partial of sum_r g_r sum_c Theta_real[r][c]^2.
-struct EpiStoreLoss {
-  double* C;
-  int64_t ldc;
-  int M, N;
+// Fused-loss S = 2 g . (G (C C^H)^-2) never stored: its epilogue forms
+// Abar / Bbar in place (as adj_hadamard does) and the loss partial
+// sum_r g_r sum_c (G (C C^H)^-2)_rc G_rc  (= sum_r g_r |Theta_r|^2).
+// In the complex case the partner lane (column 2 nu + 1 - c) supplies the
+// other half of S_{r nu}.
+struct EpiSAdj {
+  const double* G;
+  int64_t ldg;
+  double* A;
+  double* B;
+  int64_t ldab;
   const double* g;
+  int M, N;
+  int aliased;
   double* partial;
   template <class Cfg, class Acc>
   __device__ __forceinline__ void apply(const Acc (&acc)[Cfg::MI][Cfg::NI], const TileAt& at) const {
     __shared__ double red[Cfg::THREADS / ISDF_WAVE];
-    double s = 0.0;
+    double sl = 0.0;
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
@@ -109,15 +120,37 @@ struct EpiStoreLoss {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
-          if (m < M && n < N) {
-            const double v = (double)acc[i][j][r];
-            C[(int64_t)m * ldc + n] = v;
-            s += g[m] * (v * v);
+          const bool ok = m < M && n < N;
+          const double gm = ok ? g[m] : 0.0;
+          const double v = (double)acc[i][j][r];
+          const double s = 2.0 * gm * v;
+          if (ok) sl += gm * v * G[(int64_t)m * ldg + n];
+          if (aliased) {
+            if (ok) {
+              double2* a = reinterpret_cast<double2*>(A + (int64_t)m * ldab + 2 * n);
+              const double2 av = *a;
+              *a = make_double2(s * av.x, s * av.y);
+            }
+          } else {
+            const double so = __shfl_xor(s, 1, ISDF_WAVE);
+            if (ok) {
+              const int nu = n >> 1, c = n & 1;
+              const double sr = c ? so : s, si = c ? s : so;
+              if (c == 0) {
+                double2* bp = reinterpret_cast<double2*>(B + (int64_t)m * ldab + 2 * nu);
+                const double2 bv = *bp;
+                *bp = make_double2(sr * bv.x - si * bv.y, sr * bv.y + si * bv.x);
+              } else {
+                double2* ap = reinterpret_cast<double2*>(A + (int64_t)m * ldab + 2 * nu);
+                const double2 av = *ap;
+                *ap = make_double2(sr * av.x + si * av.y, sr * av.y - si * av.x);
+              }
+            }
           }
         }
       }
-    s = wave_sum(s);
-    if (at.lane == 0) red[threadIdx.x >> 6] = s;
+    sl = wave_sum(sl);
+    if (at.lane == 0) red[threadIdx.x >> 6] = sl;
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0.0;
@@ -126,6 +159,17 @@ struct EpiStoreLoss {
     }
   }
 };
+
+// Upper triangle of an n x n matrix from its lower triangle.
+__global__ void mirror_lower(double* __restrict__ H, int n, const int* abort) {
+  if (*abort) return;
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (j > i) H[e] = H[(int64_t)j * n + i];
+  }
+}
 
 __global__ void add_loss(FitState* st, const double* __restrict__ partial, int n) {
   if (st->abort) return;
@@ -209,7 +253,7 @@ static int splits_for(int64_t tiles, int64_t K) {
 struct BwdPlan {
   FitState* st;
   void *Ephi, *Epsi, *Fphi, *Fpsi, *Xphi, *Xpsi;
-  double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart;
+  double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart, *W2;
   size_t bytes;
 };
 
@@ -234,6 +278,7 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bo
   P.A = c.take<double>((size_t)rblock * 2 * n_mu);
   if (!aliased) P.B = c.take<double>((size_t)rblock * 2 * n_mu);
   P.P = c.take<double>((size_t)n1 * n1);
+  P.W2 = c.take<double>((size_t)n1 * n1);
   P.Ppart = c.take<double>((size_t)MAX_SPLITS * n1 * n1);
   P.Qphi = c.take<double>((size_t)2 * n_mu * 2 * n_phi);
   if (!aliased) P.Qpsi = c.take<double>((size_t)2 * n_mu * 2 * n_psi);
@@ -306,7 +351,9 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                        ld_psi, n_psi, idx, n_mu, nr, Xpsi);
   }
   if (!launch_ok()) return ISDF_E_HIP;
-  double* Abar = aliased ? P.A : P.B;  // after adj_hadamard
+  if (!tbar && !dgemm<KC, KC, double>(n1, n1, n1, minv, n1, minv, n1, P.W2, n1, 1.0, 0.0, 0, ab, s))
+    return ISDF_E_HIP;  // (C C^H)^-2
+  double* Abar = aliased ? P.A : P.B;  // after the Hadamard step
   double* Bbar = P.A;
   for (int64_t r = 0; r < nr; r += rblock) {
     const int rows = (int)(nr - r < rblock ? nr - r : rblock);
@@ -314,26 +361,30 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
     if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, r, rows, P.G,
                      n1, aliased ? G_REAL : G_CPLX, ab, s, P.A, aliased ? nullptr : P.B))
       return ISDF_E_HIP;
-    // Theta = G M^-1 (and the fused loss)
     if (!tbar) {
-      EpiStoreLoss epi{P.Th, n1, rows, n1, g + r, P.lpart};
-      Operand<double> a{P.G, n1, nullptr}, b{minv, n1, nullptr};
+      // H += G^T diag(g) G (lower tiles, split-K, fixed-order reduction)
+      const int64_t tiles = ceil_div(n1, 128) * ceil_div(n1, 128);
+      const int sp = splits_for(tiles / 2 + 1, rows);
+      const int64_t pn = (int64_t)n1 * n1;
+      if (!tgemm<double, XC, XC>(n1, n1, rows, P.G, n1, P.G, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
+        return ISDF_E_HIP;
+      hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, r > 0 ? 1 : 0,
+                         ab);
+      // S = 2 g . (G (C C^H)^-2): Abar / Bbar in place and the loss, in the epilogue
+      EpiSAdj epi{P.G, n1, P.A, P.B, 2 * (int64_t)n_mu, g + r, rows, n1, aliased ? 1 : 0, P.lpart};
+      Operand<double> a{P.G, n1, nullptr, nullptr}, b{P.W2, n1, nullptr, nullptr};
       if (!launch_gemm<double, 128, 128, 16, 2, 2, double, KC, double, KC, 1>(rows, n1, n1, a, b, a, b, 0, epi, 0, ab,
                                                                              s))
         return ISDF_E_HIP;
-      const int tiles = (int)(ceil_div(rows, 128) * ceil_div(n1, 128));
-      hipLaunchKernelGGL(add_loss, dim3(1), dim3(ISDF_WAVE), 0, s, P.st, (const double*)P.lpart, tiles);
-      // S = 2 g . (Theta M^-1), written over G
-      if (!dgemm<KC, KC, double>(rows, n1, n1, P.Th, n1, minv, n1, P.G, n1, 2.0, 0.0, 0, ab, s, g + r))
-        return ISDF_E_HIP;
+      const int ltiles = (int)(ceil_div(rows, 128) * ceil_div(n1, 128));
+      hipLaunchKernelGGL(add_loss, dim3(1), dim3(ISDF_WAVE), 0, s, P.st, (const double*)P.lpart, ltiles);
+      if (!launch_ok()) return ISDF_E_HIP;
     } else {
+      // Theta = G M^-1, S = Thetabar M^-1 (over G), P += Theta^T S, Abar / Bbar in place
       if (!dgemm<KC, KC, double>(rows, n1, n1, P.G, n1, minv, n1, P.Th, n1, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
       const int64_t ldt = aliased ? ld_tbar : 2 * ld_tbar;
       if (!dgemm<KC, KC, double, TT>(rows, n1, n1, tbar + r * ldt, ldt, minv, n1, P.G, n1, 1.0, 0.0, 0, ab, s))
         return ISDF_E_HIP;
-    }
-    // P += Theta^T S (split-K, fixed-order reduction)
-    {
       const int64_t tiles = ceil_div(n1, 128) * ceil_div(n1, 128);
       const int sp = splits_for(tiles, rows);
       const int64_t pn = (int64_t)n1 * n1;
@@ -341,16 +392,22 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
         return ISDF_E_HIP;
       hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, r > 0 ? 1 : 0,
                          ab);
+      hipLaunchKernelGGL(adj_hadamard, dim3(blocks_for((int64_t)rows * n_mu)), dim3(256), 0, s, (const double*)P.G,
+                         P.A, P.B, (int64_t)rows, n_mu, aliased ? 1 : 0);
+      if (!launch_ok()) return ISDF_E_HIP;
     }
-    // Abar (and Bbar) in place
-    hipLaunchKernelGGL(adj_hadamard, dim3(blocks_for((int64_t)rows * n_mu)), dim3(256), 0, s, (const double*)P.G,
-                       P.A, P.B, (int64_t)rows, n_mu, aliased ? 1 : 0);
-    if (!launch_ok()) return ISDF_E_HIP;
     if (!orbital_block<T, TS>(Abar, n_mu, Fphi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi, P.Qpart, ab, s))
       return ISDF_E_HIP;
     if (!aliased &&
         !orbital_block<T, TS>(Bbar, n_mu, Fpsi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows, P.Qpsi, P.Qpart, ab, s))
       return ISDF_E_HIP;
+  }
+  if (!tbar) {
+    // Theta^T S = 2 M^-1 H M^-2 with H = G^T diag(g) G
+    const int64_t pn = (int64_t)n1 * n1;
+    hipLaunchKernelGGL(mirror_lower, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, n1, ab);
+    if (!dgemm<KC, KC, double>(n1, n1, n1, P.P, n1, P.W2, n1, P.Ppart, n1, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
+    if (!dgemm<KC, XC, double>(n1, n1, n1, minv, n1, P.Ppart, n1, P.P, n1, 2.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
   }
   // Mbar terms at the interpolation rows
   if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu, nullptr,

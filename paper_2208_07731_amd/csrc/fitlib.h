@@ -250,14 +250,16 @@ static bool dgemm(int M, int N, int64_t K, const TA* A, int64_t lda, const doubl
 }
 
 // GEMM in compute type T with split-K slices written to C + z * zstride.
+// bscale: optional per-k factor of B; lower_only: skip tiles above the diagonal.
 template <class T, int LA, int LB, class TA, class TB, class TC>
 static bool tgemm(int M, int N, int64_t K, const TA* A, int64_t lda, const TB* B, int64_t ldb, TC* C, int64_t ldc,
                   double alpha, double beta, const int* abort, hipStream_t st, int splits = 1,
-                  int64_t zstride = 0) {
+                  int64_t zstride = 0, const double* bscale = nullptr, int lower_only = 0) {
   EpiStore<TC> epi{C, ldc, M, N, alpha, beta, nullptr, zstride};
-  Operand<TA> a{A, lda, nullptr};
-  Operand<TB> b{B, ldb, nullptr};
-  return launch_gemm<T, 128, 128, 16, 2, 2, TA, LA, TB, LB, 1>(M, N, K, a, b, a, b, 0, epi, 0, abort, st, splits);
+  Operand<TA> a{A, lda, nullptr, nullptr};
+  Operand<TB> b{B, ldb, nullptr, bscale};
+  return launch_gemm<T, 128, 128, 16, 2, 2, TA, LA, TB, LB, 1>(M, N, K, a, b, a, b, 0, epi, lower_only, abort, st,
+                                                               splits);
 }
 
 // Cholesky of X (n x n, lower, in place) and W = X^-1 into X.

@@ -54,7 +54,8 @@ template <class TS>
 struct Operand {
   const TS* p;
   int64_t ld;
-  const int* rows;  // optional gather of the x index (KC only), may be null
+  const int* rows;       // optional gather of the x index (KC only), may be null
+  const double* kscale;  // optional per-k factor: element (x, k) * kscale[k], may be null
 };
 
 struct GemmShape {
@@ -138,31 +139,40 @@ struct Stager {
         for (int e = 0; e < E; e += 2) {
           double a, b;
           load_pair<TS>(base + e, a, b);
+          if (op.kscale) {
+            a *= op.kscale[kb + e];
+            b *= op.kscale[kb + e + 1];
+          }
           v[e] = (T)a;
           v[e + 1] = (T)b;
         }
       } else {
         const bool okx = (x0 + x) < xlim;
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = (okx && kb + e < klim) ? (T)base[e] : (T)0;
+        for (int e = 0; e < E; ++e) {
+          const bool ok = okx && kb + e < klim;
+          const double f = (ok && op.kscale) ? op.kscale[kb + e] : 1.0;
+          v[e] = ok ? (T)(base[e] * f) : (T)0;
+        }
       }
     } else {
       constexpr int RUNS = X / E;  // threads per k
       const int64_t k = k0 + tid / RUNS;
       const int xb = x0 + (tid % RUNS) * E;
       const TS* base = op.p + k * op.ld + xb;
+      const double f = (op.kscale && k < klim) ? op.kscale[k] : 1.0;
       if (interior) {
 #pragma unroll
         for (int e = 0; e < E; e += 2) {
           double a, b;
           load_pair<TS>(base + e, a, b);
-          v[e] = (T)a;
-          v[e + 1] = (T)b;
+          v[e] = (T)(a * f);
+          v[e + 1] = (T)(b * f);
         }
       } else {
         const bool okk = k < klim;
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = (okk && xb + e < xlim) ? (T)base[e] : (T)0;
+        for (int e = 0; e < E; ++e) v[e] = (okk && xb + e < xlim) ? (T)(base[e] * f) : (T)0;
       }
     }
   }
