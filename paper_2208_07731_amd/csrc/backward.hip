@@ -242,11 +242,14 @@ static unsigned blocks_for(int64_t n) {
   return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
 }
 
+// Split-K factor: enough workgroups to fill the chip, slices of at least 512
+// rows, a multiple of 8 when possible (one K slice per XCD at a time).
 static int splits_for(int64_t tiles, int64_t K) {
   int s = (int)(2048 / (tiles > 0 ? tiles : 1));
   if (s > MAX_SPLITS) s = MAX_SPLITS;
   const int64_t kmax = ceil_div(K, 512);
   if (s > kmax) s = (int)kmax;
+  if (s >= 8) s -= s % 8;
   return s < 1 ? 1 : s;
 }
 
@@ -363,8 +366,8 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       return ISDF_E_HIP;
     if (!tbar) {
       // H += G^T diag(g) G (lower tiles, split-K, fixed-order reduction)
-      const int64_t tiles = ceil_div(n1, 128) * ceil_div(n1, 128);
-      const int sp = splits_for(tiles / 2 + 1, rows);
+      const int64_t tiles = gemm_tiles((int)ceil_div(n1, 128), (int)ceil_div(n1, 128), 1);
+      const int sp = splits_for(tiles, rows);
       const int64_t pn = (int64_t)n1 * n1;
       if (!tgemm<double, XC, XC>(n1, n1, rows, P.G, n1, P.G, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
         return ISDF_E_HIP;

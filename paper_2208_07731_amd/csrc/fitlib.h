@@ -228,10 +228,11 @@ static bool launch_gemm(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0,
   sh.N = N;
   sh.K = K;
   sh.kchunk = splits > 1 ? ceil_div(ceil_div(K, splits), BK) * BK : K;
-  sh.lower_only = lower_only;
+  sh.splits = splits;
+  sh.lower_only = lower_only && M == N && BM == BN;
   sh.abort = abort;
-  const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
-  dim3 grid((unsigned)tiles, 1, (unsigned)splits);
+  const int64_t tiles = gemm_tiles((int)ceil_div(M, BM), (int)ceil_div(N, BN), sh.lower_only);
+  dim3 grid((unsigned)(tiles * splits), 1, 1);
   hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, TA, LA, TB, LB, NOPS, Epi>), grid,
                      dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, epi);
   return launch_ok();

@@ -61,10 +61,16 @@ struct Operand {
 struct GemmShape {
   int M, N;
   int64_t K;
-  int64_t kchunk;    // split-K: blockIdx.z covers [z*kchunk, min(K, (z+1)*kchunk))
-  int lower_only;    // skip tiles strictly above the diagonal
+  int64_t kchunk;    // split-K slice z covers [z*kchunk, min(K, (z+1)*kchunk))
+  int splits;        // number of K slices (grid = tiles x splits, one dimension)
+  int lower_only;    // only tiles on or below the diagonal (M == N)
   const int* abort;  // nonzero *abort turns the launch into a no-op
 };
+
+// Number of tiles a launch enumerates.
+__host__ __device__ __forceinline__ int64_t gemm_tiles(int tiles_m, int tiles_n, int lower_only) {
+  return lower_only ? (int64_t)tiles_m * (tiles_m + 1) / 2 : (int64_t)tiles_m * tiles_n;
+}
 
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
   const int full = (total / 8) * 8;
@@ -301,11 +307,30 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh
   __shared__ __attribute__((aligned(16))) T smem[2 * STAGE];
   const int tiles_n = (sh.N + BN - 1) / BN;
   const int tiles_m = (sh.M + BM - 1) / BM;
-  const int logical = xcd_remap(blockIdx.x, tiles_m * tiles_n);
-  const int tm = logical / tiles_n, tn = logical % tiles_n;
+  const int ntiles = (int)gemm_tiles(tiles_m, tiles_n, sh.lower_only);
+  const int bid = blockIdx.x;
+  int z, logical;
+  if (sh.splits > 1 && sh.splits % 8 == 0) {
+    // split-K: each XCD owns whole K slices (z = xcd, xcd + 8, ...), so the
+    // operands of a slice are fetched into one L2 and shared by every tile
+    const int xcd = bid % 8, q = bid / 8;
+    z = xcd + 8 * (q / ntiles);
+    logical = q % ntiles;
+  } else {
+    z = bid / ntiles;
+    logical = xcd_remap(bid % ntiles, ntiles);
+  }
+  int tm, tn;
+  if (sh.lower_only) {  // row-major enumeration of the lower triangle of tiles
+    tm = (int)((sqrt(8.0 * logical + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(tm + 1) * (tm + 2) / 2 <= logical) ++tm;
+    while ((int64_t)tm * (tm + 1) / 2 > logical) --tm;
+    tn = logical - tm * (tm + 1) / 2;
+  } else {
+    tm = logical / tiles_n;
+    tn = logical % tiles_n;
+  }
   const int m0 = tm * BM, n0 = tn * BN;
-  if (sh.lower_only && n0 > m0 + BM - 1) return;
-  const int z = blockIdx.z;
   const int64_t kbeg = (int64_t)z * sh.kchunk;
   const int64_t kend = kbeg + sh.kchunk < sh.K ? kbeg + sh.kchunk : sh.K;
 

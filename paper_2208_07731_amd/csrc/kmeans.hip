@@ -54,7 +54,7 @@ struct KmGeom {
 };
 
 constexpr int ASSIGN_THREADS = 256;  // 4 wavefronts = 4 bricks
-constexpr int CTILE = 1024;          // centroids staged per LDS tile
+constexpr int CTILE = 2048;          // centroids staged per LDS tile
 
 // Squared distance with the same operation order as the definition
 // ((s0 dx^2 + s1 dy^2) + s2 dz^2); contraction off so that the value is the
@@ -160,11 +160,31 @@ __global__ void km_init(KmArrays a, const double* __restrict__ c0, int K, int T,
 }
 
 // ------------------------------------------------------------------ assign
+// Exact per-brick candidate pruning.  For the brick's bounding box B and a
+// centroid c: lb(c) = min_{p in B} D(p, c), ub(c) = max_{p in B} D(p, c).
+// U = min_c ub(c) bounds every point's nearest distance, so a centroid with
+// lb(c) > U is strictly farther than some centroid for every point of the
+// brick and can be skipped.  The test uses U (1 + margin) with margin well
+// above rounding and above the near-tie band, so labels, exact ties and
+// near-tie counts are those of the full scan.  Survivors are evaluated in
+// increasing centroid order (lowest index wins ties).
+constexpr int SURV = 128;  // per-wavefront survivor list
+
+__device__ __forceinline__ double axis_lb(double c, double lo, double hi) {
+  const double d = fmax(fmax(lo - c, c - hi), 0.0);
+  return d * d;
+}
+__device__ __forceinline__ double axis_ub(double c, double lo, double hi) {
+  const double d = fmax(fabs(c - lo), fabs(c - hi));
+  return d * d;
+}
+
 __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g, int K, int t,
                                                             double near_rel) {
   if (a.st->done) return;
   __shared__ double cx[CTILE], cy[CTILE], cz[CTILE];
   __shared__ double jw[ASSIGN_THREADS / ISDF_WAVE];
+  __shared__ int surv[ASSIGN_THREADS / ISDF_WAVE][SURV];
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -180,10 +200,16 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
   const int pi = bi * 4 + (lane >> 4), pj = bj * 4 + ((lane >> 2) & 3), pk = bk * 4 + (lane & 3);
   const bool valid = brick < nbricks && pi < g.n0 && pj < g.n1 && pk < g.n2;
   const double px = (double)pi, py = (double)pj, pz = (double)pk;
+  // bounding box of the brick's grid points
+  const double lo0 = bi * 4, lo1 = bj * 4, lo2 = bk * 4;
+  const double hi0 = min(bi * 4 + 3, g.n0 - 1), hi1 = min(bj * 4 + 3, g.n1 - 1), hi2 = min(bk * 4 + 3, g.n2 - 1);
+  const double margin = 1.0 + fmax(1e-5, 4.0 * near_rel);
+  int* list = surv[wv];
 
-  double d1 = DBL_MAX, d2 = DBL_MAX;
+  double d1 = INFINITY, d2 = INFINITY;
   int lab = 0;
-  bool first = true;
+  // pass 1: U = min over centroids of the farthest brick distance
+  double U = INFINITY;
   for (int c0 = 0; c0 < K; c0 += CTILE) {
     const int cn = min(CTILE, K - c0);
     __syncthreads();
@@ -193,21 +219,60 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
       cz[i] = a.cent[3 * (int64_t)(c0 + i) + 2];
     }
     __syncthreads();
-    int m = 0;
-    if (first) {  // d1 <- centroid 0, so that DBL_MAX never masks a real distance
-      d1 = sqd(px - cx[0], py - cy[0], pz - cz[0], g);
-      d2 = INFINITY;
-      lab = 0;
-      m = 1;
-      first = false;
+    for (int m = lane; m < cn; m += ISDF_WAVE) {
+      const double ub = (g.s0 * axis_ub(cx[m], lo0, hi0) + g.s1 * axis_ub(cy[m], lo1, hi1)) +
+                        g.s2 * axis_ub(cz[m], lo2, hi2);
+      U = fmin(U, ub);
     }
-#pragma unroll 4
-    for (; m < cn; ++m) {
-      double d = sqd(px - cx[m], py - cy[m], pz - cz[m], g);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) U = fmin(U, __shfl_xor(U, o, ISDF_WAVE));
+  const double cut = U * margin;
+  // pass 2: survivors of each tile, in increasing index, then the exact scan
+  const bool one_tile = K <= CTILE;
+  for (int c0 = 0; c0 < K; c0 += CTILE) {
+    const int cn = min(CTILE, K - c0);
+    if (!one_tile) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < cn; i += ASSIGN_THREADS) {
+        cx[i] = a.cent[3 * (int64_t)(c0 + i) + 0];
+        cy[i] = a.cent[3 * (int64_t)(c0 + i) + 1];
+        cz[i] = a.cent[3 * (int64_t)(c0 + i) + 2];
+      }
+      __syncthreads();
+    }
+    int nlist = 0;
+    for (int mb = 0; mb < cn; mb += ISDF_WAVE) {
+      const int m = mb + lane;
+      bool keep = false;
+      if (m < cn) {
+        const double lb = (g.s0 * axis_lb(cx[m], lo0, hi0) + g.s1 * axis_lb(cy[m], lo1, hi1)) +
+                          g.s2 * axis_lb(cz[m], lo2, hi2);
+        keep = lb <= cut;
+      }
+      const unsigned long long bal = __ballot(keep);
+      const int cnt = __popcll(bal);
+      if (nlist + cnt > SURV) {  // flush the list (wave-uniform)
+        for (int q = 0; q < nlist; ++q) {
+          const int mm = list[q];
+          const double d = sqd(px - cx[mm], py - cy[mm], pz - cz[mm], g);
+          d2 = fmin(d2, fmax(d, d1));
+          const bool better = d < d1;
+          d1 = better ? d : d1;
+          lab = better ? c0 + mm : lab;
+        }
+        nlist = 0;
+      }
+      if (keep) list[nlist + __popcll(bal & ((1ull << lane) - 1ull))] = m;
+      nlist += cnt;
+    }
+    for (int q = 0; q < nlist; ++q) {
+      const int mm = list[q];
+      const double d = sqd(px - cx[mm], py - cy[mm], pz - cz[mm], g);
       d2 = fmin(d2, fmax(d, d1));
-      bool better = d < d1;
+      const bool better = d < d1;
       d1 = better ? d : d1;
-      lab = better ? c0 + m : lab;
+      lab = better ? c0 + mm : lab;
     }
   }
 
