@@ -39,14 +39,12 @@ static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   FitPlan P{};
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   const int n1 = aliased ? n_mu : 2 * n_mu;
-  const int nblk = (int)ceil_div(n1, NB);
   P.st = c.take<FitState>(1);
   P.marker = c.take<int>(nr);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
   P.Epsi = aliased ? nullptr : c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize);
-  P.inv.dinv = c.take<double>((size_t)nblk * NB * NB);
   P.inv.Y = c.take<double>((size_t)n1 * n1);
-  P.inv.R = c.take<double>((size_t)NB * n1);
+  P.inv.R = c.take<double>((size_t)n1 * n1);
   P.G = c.take<double>((size_t)rblock * n1);
   P.bytes = c.used;
   return P;

@@ -135,18 +135,21 @@ struct EpiGram {
 };
 
 // ------------------------------------------------------------ Cholesky
-// Factors the kb x kb diagonal block at (k0, k0) of X in place (lower), and
-// writes its inverse to dinv (kb x kb, ld NB) and to the diagonal block of Y.
+// Factors the kb x kb diagonal block at (k0, k0) of X in place (lower) and
+// writes its inverse into the same block of Y.  The inverse is reduced
+// alongside the elimination (L X = I solved row by row: at step j,
+// X_j = R_j / l_jj and R_i -= l_ij X_j for i > j), so it costs no extra
+// synchronisation.
 __global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ X, int64_t ldx, int k0, int kb,
-                                                  double* __restrict__ dinv, double* __restrict__ Y,
-                                                  int64_t ldy, FitState* st) {
+                                                  double* __restrict__ Y, int64_t ldy, FitState* st) {
   if (st->abort) return;
   __shared__ double a[NB][NB + 1];
-  __shared__ double li[NB][NB + 1];
+  __shared__ double r[NB][NB + 1];
   const int tid = threadIdx.x;
   for (int e = tid; e < kb * kb; e += 256) {
     const int i = e / kb, j = e % kb;
     a[i][j] = j <= i ? X[(int64_t)(k0 + i) * ldx + k0 + j] : 0.0;
+    r[i][j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
   int failed = -1;
@@ -163,12 +166,19 @@ __global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ X, int64_
       atomic_min_pos(&st->pmin, piv);
       atomic_max_pos(&st->pmax, piv);
     }
-    for (int i = j + 1 + tid; i < kb; i += 256) a[i][j] /= l;
+    for (int e = tid; e < kb; e += 256) {
+      if (e > j) a[e][j] /= l;
+      else r[j][e] /= l;
+    }
     __syncthreads();
     const int w = kb - j - 1;
     for (int e = tid; e < w * w; e += 256) {
       const int i = j + 1 + e / w, c = j + 1 + e % w;
       if (c <= i) a[i][c] -= a[i][j] * a[c][j];
+    }
+    for (int e = tid; e < w * (j + 1); e += 256) {
+      const int i = j + 1 + e / (j + 1), c = e % (j + 1);
+      r[i][c] -= a[i][j] * r[j][c];
     }
     __syncthreads();
   }
@@ -182,22 +192,7 @@ __global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ X, int64_
   for (int e = tid; e < kb * kb; e += 256) {
     const int i = e / kb, j = e % kb;
     if (j <= i) X[(int64_t)(k0 + i) * ldx + k0 + j] = a[i][j];
-  }
-  // inverse of the lower-triangular block, one column per thread
-  if (tid < kb) {
-    const int c = tid;
-    for (int i = 0; i < c; ++i) li[i][c] = 0.0;
-    for (int i = c; i < kb; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= a[i][k] * li[k][c];
-      li[i][c] = s / a[i][i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e % kb;
-    dinv[i * NB + j] = li[i][j];
-    Y[(int64_t)(k0 + i) * ldy + k0 + j] = li[i][j];
+    Y[(int64_t)(k0 + i) * ldy + k0 + j] = j <= i ? r[i][j] : 0.0;
   }
 }
 
@@ -221,7 +216,7 @@ template <class T, int BM, int BN, int BK, int WM, int WN, class TA, int LA, cla
           class Epi>
 static bool launch_gemm(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0, Operand<TA> A1,
                         Operand<TB> B1, int64_t K1, const Epi& epi, int lower_only, const int* abort,
-                        hipStream_t st, int splits = 1) {
+                        hipStream_t st, int splits = 1, int batch = 1, int64_t sa = 0, int64_t sb = 0) {
   if (M <= 0 || N <= 0) return true;
   GemmShape sh;
   sh.M = M;
@@ -231,8 +226,10 @@ static bool launch_gemm(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0,
   sh.splits = splits;
   sh.lower_only = lower_only && M == N && BM == BN;
   sh.abort = abort;
+  sh.sa = sa;
+  sh.sb = sb;
   const int64_t tiles = gemm_tiles((int)ceil_div(M, BM), (int)ceil_div(N, BN), sh.lower_only);
-  dim3 grid((unsigned)(tiles * splits), 1, 1);
+  dim3 grid((unsigned)(tiles * splits), (unsigned)batch, 1);
   hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, TA, LA, TB, LB, NOPS, Epi>), grid,
                      dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, epi);
   return launch_ok();
@@ -243,11 +240,23 @@ template <int LA, int LB, class TC, class TA = double>
 static bool dgemm(int M, int N, int64_t K, const TA* A, int64_t lda, const double* B, int64_t ldb, TC* C,
                   int64_t ldc, double alpha, double beta, int lower_only, const int* abort, hipStream_t st,
                   const double* rowscale = nullptr) {
-  EpiStore<TC> epi{C, ldc, M, N, alpha, beta, rowscale, 0};
+  EpiStore<TC> epi{C, ldc, M, N, alpha, beta, rowscale, 0, 0};
   Operand<TA> a{A, lda, nullptr};
   Operand<double> b{B, ldb, nullptr};
   return launch_gemm<double, 128, 128, 16, 2, 2, TA, LA, double, LB, 1>(M, N, K, a, b, a, b, 0, epi, lower_only,
                                                                        abort, st);
+}
+
+// Batched FP64 GEMM: batch b uses A + b sa, B + b sb, C + b sc.
+template <int LA, int LB>
+static bool dgemm_batched(int M, int N, int64_t K, const double* A, int64_t lda, int64_t sa, const double* B,
+                          int64_t ldb, int64_t sb, double* C, int64_t ldc, int64_t sc, int batch, double alpha,
+                          const int* abort, hipStream_t st) {
+  EpiStore<double> epi{C, ldc, M, N, alpha, 0.0, nullptr, 0, sc};
+  Operand<double> a{A, lda, nullptr, nullptr};
+  Operand<double> b{B, ldb, nullptr, nullptr};
+  return launch_gemm<double, 128, 128, 16, 2, 2, double, LA, double, LB, 1>(M, N, K, a, b, a, b, 0, epi, 0, abort, st,
+                                                                           1, batch, sa, sb);
 }
 
 // GEMM in compute type T with split-K slices written to C + z * zstride.
@@ -256,18 +265,23 @@ template <class T, int LA, int LB, class TA, class TB, class TC>
 static bool tgemm(int M, int N, int64_t K, const TA* A, int64_t lda, const TB* B, int64_t ldb, TC* C, int64_t ldc,
                   double alpha, double beta, const int* abort, hipStream_t st, int splits = 1,
                   int64_t zstride = 0, const double* bscale = nullptr, int lower_only = 0) {
-  EpiStore<TC> epi{C, ldc, M, N, alpha, beta, nullptr, zstride};
+  EpiStore<TC> epi{C, ldc, M, N, alpha, beta, nullptr, zstride, 0};
   Operand<TA> a{A, lda, nullptr, nullptr};
   Operand<TB> b{B, ldb, nullptr, bscale};
   return launch_gemm<T, 128, 128, 16, 2, 2, TA, LA, TB, LB, 1>(M, N, K, a, b, a, b, 0, epi, lower_only, abort, st,
                                                                splits);
 }
 
-// Cholesky of X (n x n, lower, in place) and W = X^-1 into X.
+// Cholesky of X (n x n, lower, in place) and W = X^-1 into X:
+//  1. blocked right-looking Cholesky, 64-wide diagonal blocks factored and
+//     inverted in LDS, panel L21 = A21 L11^-T and trailing update on MFMA;
+//  2. Y = L^-1 by recursive doubling: once every aligned segment of size b
+//     has its inverse, a pair [[A, 0], [L21, C]] gets its lower-left block
+//     -C^-1 L21 A^-1 (two GEMMs, batched over all pairs of the level);
+//  3. W = Y^T Y.
 struct InvWork {
-  double* dinv;  // [nblk][NB][NB]
-  double* Y;     // [n][n]
-  double* R;     // [NB][n]
+  double* Y;  // [n][n]
+  double* R;  // [n][n] scratch
 };
 
 static int spd_inverse(double* X, int n, InvWork w, FitState* st, hipStream_t s) {
@@ -276,26 +290,42 @@ static int spd_inverse(double* X, int n, InvWork w, FitState* st, hipStream_t s)
   if (!fill<double>(w.Y, (int64_t)n * n, 0.0, s)) return ISDF_E_HIP;
   for (int b = 0; b < nblk; ++b) {
     const int k0 = b * NB, kb = n - k0 < NB ? n - k0 : NB;
-    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, X, (int64_t)n, k0, kb, w.dinv + (int64_t)b * NB * NB,
-                       w.Y, (int64_t)n, st);
+    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, X, (int64_t)n, k0, kb, w.Y, (int64_t)n, st);
     if (!launch_ok()) return ISDF_E_HIP;
     const int rest = n - k0 - kb;
     if (rest <= 0) continue;
     double* P = X + (int64_t)(k0 + kb) * n + k0;
     // panel: L21 = A21 L11^-T (in place: each workgroup reads all K of its rows before writing them)
-    if (!dgemm<KC, KC>(rest, kb, kb, P, n, w.dinv + (int64_t)b * NB * NB, NB, P, n, 1.0, 0.0, 0, ab, s))
+    if (!dgemm<KC, KC>(rest, kb, kb, P, n, w.Y + (int64_t)k0 * n + k0, n, P, n, 1.0, 0.0, 0, ab, s))
       return ISDF_E_HIP;
     // trailing: A22 -= L21 L21^T (lower tiles)
     double* T = X + (int64_t)(k0 + kb) * n + (k0 + kb);
     if (!dgemm<KC, KC>(rest, rest, kb, P, n, P, n, T, n, -1.0, 1.0, 1, ab, s)) return ISDF_E_HIP;
   }
-  // Y = L^-1 by block rows: Y_i,<i = -Dinv_i (L_i,<i Y_<i,<i)
-  for (int b = 1; b < nblk; ++b) {
-    const int k0 = b * NB, kb = n - k0 < NB ? n - k0 : NB;
-    if (!dgemm<KC, XC>(kb, k0, k0, X + (int64_t)k0 * n, n, w.Y, n, w.R, n, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
-    if (!dgemm<KC, XC>(kb, k0, kb, w.dinv + (int64_t)b * NB * NB, NB, w.R, n, w.Y + (int64_t)k0 * n, n, -1.0, 0.0,
-                       0, ab, s))
-      return ISDF_E_HIP;
+  const int64_t ld = n;
+  for (int b = NB; b < n; b *= 2) {
+    const int pairs = n / (2 * b);
+    const int64_t step = 2 * (int64_t)b * (ld + 1);  // from one pair's origin to the next
+    if (pairs > 0) {
+      // R_p = L21 A^-1, then C-block rows of Y: -C^-1 R_p
+      if (!dgemm_batched<KC, XC>(b, b, b, X + (int64_t)b * ld, ld, step, w.Y, ld, step, w.R, b, (int64_t)b * b,
+                                 pairs, 1.0, ab, s))
+        return ISDF_E_HIP;
+      if (!dgemm_batched<KC, XC>(b, b, b, w.Y + (int64_t)b * ld + b, ld, step, w.R, b, (int64_t)b * b,
+                                 w.Y + (int64_t)b * ld, ld, step, pairs, -1.0, ab, s))
+        return ISDF_E_HIP;
+    }
+    const int o = pairs * 2 * b, rem = n - o;
+    if (rem > b) {  // ragged last pair: A of size b, C of size rem - b
+      const int c = rem - b;
+      const int64_t org = (int64_t)o * (ld + 1);
+      if (!dgemm_batched<KC, XC>(c, b, b, X + org + (int64_t)b * ld, ld, 0, w.Y + org, ld, 0, w.R, b, 0, 1, 1.0, ab,
+                                 s))
+        return ISDF_E_HIP;
+      if (!dgemm_batched<KC, XC>(c, b, c, w.Y + org + (int64_t)b * ld + b, ld, 0, w.R, b, 0,
+                                 w.Y + org + (int64_t)b * ld, ld, 0, 1, -1.0, ab, s))
+        return ISDF_E_HIP;
+    }
   }
   // W = Y^T Y
   if (!dgemm<XC, XC>(n, n, n, w.Y, n, w.Y, n, X, n, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;

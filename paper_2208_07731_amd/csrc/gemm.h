@@ -65,6 +65,7 @@ struct GemmShape {
   int splits;        // number of K slices (grid = tiles x splits, one dimension)
   int lower_only;    // only tiles on or below the diagonal (M == N)
   const int* abort;  // nonzero *abort turns the launch into a no-op
+  int64_t sa, sb;    // batch strides of A and B (elements); batch index = blockIdx.y
 };
 
 // Number of tiles a launch enumerates.
@@ -292,6 +293,7 @@ struct TileAt {
   int m_wave, n_wave;  // first row / column of this wavefront's sub-tile
   int lane;
   int z;               // split-K index
+  int batch;           // batch index
 };
 
 // Generic kernel: NOPS = 1 (one operand pair) or 2 (two pairs into two
@@ -331,6 +333,11 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh
     tn = logical % tiles_n;
   }
   const int m0 = tm * BM, n0 = tn * BN;
+  const int batch = blockIdx.y;
+  if (batch) {
+    A0.p += batch * sh.sa;
+    B0.p += batch * sh.sb;
+  }
   const int64_t kbeg = (int64_t)z * sh.kchunk;
   const int64_t kend = kbeg + sh.kchunk < sh.K ? kbeg + sh.kchunk : sh.K;
 
@@ -344,7 +351,7 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int wm = wv / (BN / Cfg::WTN), wn = wv % (BN / Cfg::WTN);
-  TileAt at{m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, z};
+  TileAt at{m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, z, batch};
   if constexpr (NOPS == 2) {
     typename MfmaT<T>::acc_t acc1[Cfg::MI][Cfg::NI];
 #pragma unroll
@@ -370,9 +377,10 @@ struct EpiStore {
   double alpha, beta;
   const double* rowscale;  // may be null
   int64_t zstride;
+  int64_t bstride;  // batch stride of C
   template <class Cfg, class Acc>
   __device__ __forceinline__ void apply(const Acc (&acc)[Cfg::MI][Cfg::NI], const TileAt& at) const {
-    TC* Cz = C + at.z * zstride;
+    TC* Cz = C + at.z * zstride + at.batch * bstride;
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll

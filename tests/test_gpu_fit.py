@@ -150,3 +150,34 @@ def test_fit_not_positive_definite():
     t = dev(big)
     _, _, info = isdf.fit(t[:, :7], None, dev(idx), grid=(5, 6, 7), check=False)
     assert info["status"] == 1 and info["pivot"] == 0
+
+
+@pytest.mark.parametrize("n_mu,aliased", [(37, True), (100, True), (200, False), (130, True), (97, False)])
+def test_minv_ragged_orders(n_mu, aliased):
+    """(C C^H)^-1 for orders that are not multiples of the 64-wide diagonal
+    blocks or of the doubling levels of the triangular inverse."""
+    rng = np.random.default_rng(n_mu)
+    nr = 9 * 9 * 9
+    phi = rng.standard_normal((nr, 24)) + 1j * rng.standard_normal((nr, 24))
+    psi = phi if aliased else rng.standard_normal((nr, 20)) + 1j * rng.standard_normal((nr, 20))
+    idx = rng.choice(nr, n_mu, replace=False).astype(np.int32)
+    pt = dev(phi)
+    st = pt if aliased else dev(psi)
+    theta, minv, info = isdf.fit(pt, None if aliased else st, dev(idx))
+    ref = oracle.fit(phi, psi, idx)
+    kappa = oracle.cc_condition(phi, psi, idx)
+    assert info["status"] == 0
+    th = theta.cpu().numpy()
+    want = ref["theta"].real if aliased else ref["theta"]
+    assert rel(th, want) <= fp64_tol(kappa)
+    n1 = n_mu if aliased else 2 * n_mu
+    W = minv.cpu().numpy().reshape(n1, n1)
+    M = ref["M"]
+    if not aliased:  # real 2x2-block form of the complex matrix
+        Me = np.zeros((n1, n1))
+        Me[0::2, 0::2] = M.real
+        Me[0::2, 1::2] = M.imag
+        Me[1::2, 0::2] = -M.imag
+        Me[1::2, 1::2] = M.real
+        M = Me
+    assert np.linalg.norm(W @ M.real - np.eye(n1)) <= 1e2 * kappa * EPS * np.sqrt(n1)
