@@ -30,10 +30,16 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of what defines the solve GEMM: the kernel template (gemm.h) and
+    the lines of fitlib.h that instantiate the FP64 tile configuration."""
+    csrc = os.path.join(ROOT, "paper_2208_07731_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("gemm.h", "fitlib.h", "fit.hip"):
-        with open(os.path.join(ROOT, "paper_2208_07731_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "gemm.h"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(csrc, "fitlib.h")) as fh:
+        for line in fh:
+            if "launch_gemm<double, " in line:
+                h.update(line.encode())
     return h.hexdigest()[:16]
 
 
@@ -118,6 +124,8 @@ def main():
     ap.add_argument("--prec", default="fp64")
     ap.add_argument("--mixed", default="fp32", help="second Gram precision to time ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the ISDF path here has no "
@@ -141,6 +149,14 @@ def main():
         phi = psi[:, : wl.n_phi]
     g = torch.as_tensor(d["g"]).cuda()
     torch.cuda.synchronize()
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
 
     def run(prec, steps, warmup):
         st = ISDFStep(phi, None if wl.aliased else psi, wl.n_mu, d["c0"], wl.kmeans_iters, g=g, prec=prec)

@@ -138,49 +138,50 @@ struct EpiGram {
 // Factors the kb x kb diagonal block at (k0, k0) of X in place (lower) and
 // writes its inverse into the same block of Y.  The inverse is reduced
 // alongside the elimination (L X = I solved row by row: at step j,
-// X_j = R_j / l_jj and R_i -= l_ij X_j for i > j), so it costs no extra
-// synchronisation.
+// X_j = R_j / l_jj and R_i -= l_ij X_j for i > j).  Step j updates with the
+// unscaled column j and 1 / pivot; column j (and row j of R) are scaled at
+// the start of step j + 1, when nothing reads them any more, so each step
+// needs a single barrier.  Threads form a 16 x 16 grid over (row, column).
 __global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ X, int64_t ldx, int k0, int kb,
                                                   double* __restrict__ Y, int64_t ldy, FitState* st) {
   if (st->abort) return;
   __shared__ double a[NB][NB + 1];
   __shared__ double r[NB][NB + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e % kb;
-    a[i][j] = j <= i ? X[(int64_t)(k0 + i) * ldx + k0 + j] : 0.0;
-    r[i][j] = i == j ? 1.0 : 0.0;
-  }
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int i = ty; i < kb; i += 16)
+    for (int j = tx; j < kb; j += 16) {
+      a[i][j] = j <= i ? X[(int64_t)(k0 + i) * ldx + k0 + j] : 0.0;
+      r[i][j] = i == j ? 1.0 : 0.0;
+    }
   __syncthreads();
   int failed = -1;
+  double il_prev = 0.0;
   for (int j = 0; j < kb; ++j) {
     const double piv = a[j][j];
     if (!(piv > 0.0) || !(piv < INFINITY)) {
       failed = j;
       break;
     }
-    const double l = sqrt(piv);
-    __syncthreads();
+    if (j > 0) {  // scale column j - 1 of L and row j - 1 of the inverse
+      const int p = j - 1;
+      if (tid < kb) {
+        if (tid > p) a[tid][p] *= il_prev;
+        else r[p][tid] *= il_prev;
+      }
+    }
+    const double l = sqrt(piv), ip = 1.0 / piv;
     if (tid == 0) {
-      a[j][j] = l;
       atomic_min_pos(&st->pmin, piv);
       atomic_max_pos(&st->pmax, piv);
     }
-    for (int e = tid; e < kb; e += 256) {
-      if (e > j) a[e][j] /= l;
-      else r[j][e] /= l;
+    for (int i = j + 1 + ty; i < kb; i += 16) {
+      const double aij = a[i][j] * ip;
+      for (int c = j + 1 + tx; c <= i; c += 16) a[i][c] -= aij * a[c][j];
+      for (int c = tx; c <= j; c += 16) r[i][c] -= aij * r[j][c];
     }
     __syncthreads();
-    const int w = kb - j - 1;
-    for (int e = tid; e < w * w; e += 256) {
-      const int i = j + 1 + e / w, c = j + 1 + e % w;
-      if (c <= i) a[i][c] -= a[i][j] * a[c][j];
-    }
-    for (int e = tid; e < w * (j + 1); e += 256) {
-      const int i = j + 1 + e / (j + 1), c = e % (j + 1);
-      r[i][c] -= a[i][j] * r[j][c];
-    }
-    __syncthreads();
+    if (tid == 0) a[j][j] = l;  // read again only by the scaling of step j + 1
+    il_prev = 1.0 / l;
   }
   if (failed >= 0) {
     if (tid == 0) {
@@ -189,11 +190,19 @@ __global__ __launch_bounds__(256) void potrf_diag(double* __restrict__ X, int64_
     }
     return;
   }
-  for (int e = tid; e < kb * kb; e += 256) {
-    const int i = e / kb, j = e % kb;
-    if (j <= i) X[(int64_t)(k0 + i) * ldx + k0 + j] = a[i][j];
-    Y[(int64_t)(k0 + i) * ldy + k0 + j] = j <= i ? r[i][j] : 0.0;
+  {  // scale the last column / row
+    const int p = kb - 1;
+    if (tid < kb) {
+      if (tid > p) a[tid][p] *= il_prev;
+      else r[p][tid] *= il_prev;
+    }
   }
+  __syncthreads();
+  for (int i = ty; i < kb; i += 16)
+    for (int j = tx; j < kb; j += 16) {
+      if (j <= i) X[(int64_t)(k0 + i) * ldx + k0 + j] = a[i][j];
+      Y[(int64_t)(k0 + i) * ldy + k0 + j] = j <= i ? r[i][j] : 0.0;
+    }
 }
 
 __global__ void fit_finish(const FitState* st, isdf_fit_info* info, double* loss_out, int backward) {
