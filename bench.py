@@ -122,7 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="water64")
     ap.add_argument("--prec", default="fp64")
-    ap.add_argument("--mixed", default="fp32", help="second Gram precision to time ('' to skip)")
+    ap.add_argument("--mixed", default="bf16x6,fp16x3,fp32",
+                    help="comma-separated orbital-contraction precisions to time beside --prec ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
@@ -206,12 +207,16 @@ def main():
         theta64 = st.theta.clone()
         del st
         torch.cuda.empty_cache()
-        log(f"[bench] {args.mixed}: timing")
-        st2, ms2, _, ph2, _ = run(args.mixed, args.steps, args.warmup)
-        err = float(torch.linalg.norm(st2.theta.double() - theta64) / torch.linalg.norm(theta64))
-        out["mixed"] = {"gram_prec": args.mixed, "ms_per_step": round(ms2, 3), "phases_ms": ph2,
-                        "theta_rel_err_vs_fp64_gpu": err, "speedup": round(ms / ms2, 3)}
-        del st2, theta64
+        out["mixed"] = {}
+        for prec in [p for p in args.mixed.split(",") if p]:
+            log(f"[bench] {prec}: timing")
+            st2, ms2, _, ph2, _ = run(prec, args.steps, args.warmup)
+            err = float(torch.linalg.norm(st2.theta.double() - theta64) / torch.linalg.norm(theta64))
+            out["mixed"][prec] = {"ms_per_step": round(ms2, 3), "phases_ms": ph2,
+                                  "theta_rel_err_vs_fp64_gpu": err, "speedup_vs_fp64": round(ms / ms2, 3)}
+            del st2
+            torch.cuda.empty_cache()
+        del theta64
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         c0 = np.asarray(d["c0"], dtype=np.int64)  # seeds are distinct grid points

@@ -257,6 +257,8 @@ struct BwdPlan {
   FitState* st;
   void *Ephi, *Epsi, *Fphi, *Fpsi, *Xphi, *Xpsi;
   double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart, *W2;
+  double* amax;  // [4] max |Phi|, |Psi|, |Abar|, |Bbar| (binary16 split)
+  double* sc;    // [8] operand scales: Gram (4), dPhi (2), dPsi (2)
   size_t bytes;
 };
 
@@ -268,6 +270,8 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bo
   const int64_t n1 = aliased ? n_mu : 2 * (int64_t)n_mu;
   const int nmax = n_phi > n_psi ? n_phi : n_psi;
   P.st = c.take<FitState>(1);
+  P.amax = c.take<double>(4);
+  P.sc = c.take<double>(8);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
   P.Fphi = c.take<char>((size_t)2 * n_phi * 2 * n_mu * tsize);
   P.Xphi = c.take<char>((size_t)n_mu * 2 * n_phi * tsize);
@@ -296,29 +300,48 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bo
   return P;
 }
 
-// One orbital set's share of the block: dX rows = Abar F, Q += Abar^T X.
-template <class T, class TS>
-static bool orbital_block(const double* Abar, int n_mu, const T* F, const TS* X, int64_t ld_x, int n, TS* dX,
-                          int64_t ld_dx, int64_t r, int rows, double* Q, double* Qpart, const int* ab,
-                          hipStream_t s) {
+// dX rows = Abar F (Abar: rows x 2 N_mu real form, F: packed Phi_mu) in the
+// orbital precision; scales = binary16 operand scales (FP16 split only).
+template <int PREC, class TS>
+static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec<PREC>::E* F, int n, TS* dX,
+                     int64_t ld_dx, const double* scales, const int* ab, hipStream_t s) {
+  typedef typename Prec<PREC>::E T;
+  constexpr int SPLIT = Prec<PREC>::SPLIT;
   const int64_t two_mu = 2 * (int64_t)n_mu;
-  if (!tgemm<T, KC, KC>(rows, 2 * n, two_mu, Abar, two_mu, F, two_mu, dX + 2 * r * ld_dx, 2 * ld_dx, 1.0, 0.0, ab,
-                        s))
-    return false;
+  if constexpr (SPLIT >= 0) {
+    EpiStore<TS> epi{dX, 2 * ld_dx, rows, 2 * n, 1.0, 0.0, nullptr, 0, 0};
+    Operand<double> a{Abar, two_mu, nullptr, nullptr};
+    Operand<T> b{F, two_mu, nullptr, nullptr};
+    return launch_split<SPLIT, 128, 64, 2, 2, double, T, 1>(rows, 2 * n, two_mu, a, b, a, b, 0,
+                                                            SPLIT == SPLIT_FP16X3 ? scales : nullptr, epi, ab, s);
+  } else {
+    return tgemm<T, KC, KC>(rows, 2 * n, two_mu, Abar, two_mu, F, two_mu, dX, 2 * ld_dx, 1.0, 0.0, ab, s);
+  }
+}
+
+// One orbital set's share of the block: dX rows = Abar F, Q += Abar^T X.
+template <int PREC, class TS>
+static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const TS* X, int64_t ld_x,
+                          int n, TS* dX, int64_t ld_dx, int64_t r, int rows, double* Q, double* Qpart,
+                          const double* scales, const int* ab, hipStream_t s) {
+  const int64_t two_mu = 2 * (int64_t)n_mu;
+  if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, n, dX + 2 * r * ld_dx, ld_dx, scales, ab, s)) return false;
   const int64_t tiles = ceil_div(two_mu, 128) * ceil_div(2 * n, 128);
   const int sp = splits_for(tiles, rows);
   const int64_t qn = two_mu * 2 * n;
-  if (!tgemm<T, XC, XC>((int)two_mu, 2 * n, rows, Abar, two_mu, X + 2 * r * ld_x, 2 * ld_x, Qpart, 2 * (int64_t)n,
-                        1.0, 0.0, ab, s, sp, qn))
+  if (!tgemm<typename Prec<PREC>::Q, XC, XC>((int)two_mu, 2 * n, rows, Abar, two_mu, X + 2 * r * ld_x, 2 * ld_x,
+                                             Qpart, 2 * (int64_t)n, 1.0, 0.0, ab, s, sp, qn))
     return false;
   hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(qn)), dim3(256), 0, s, Q, Qpart, qn, sp, r > 0 ? 1 : 0, ab);
   return launch_ok();
 }
 
-// Mbar terms of one orbital set at the interpolation rows.
-template <class T, class TS>
-static bool orbital_fix(const double* dAbar, int n_mu, const T* F, const T* Xmu, int n, TS* dX, int64_t ld_dx,
-                        const int32_t* idx, double* Q, double* T1, const int* ab, hipStream_t s) {
+// Mbar terms of one orbital set at the interpolation rows (small: N_mu rows).
+template <int PREC, class TS>
+static bool orbital_fix(const double* dAbar, int n_mu, const typename Prec<PREC>::E* F,
+                        const typename Prec<PREC>::E* Xmu, int n, TS* dX, int64_t ld_dx, const int32_t* idx, double* Q,
+                        double* T1, const int* ab, hipStream_t s) {
+  typedef typename Prec<PREC>::E T;
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if (!tgemm<T, KC, KC>(n_mu, 2 * n, two_mu, dAbar, two_mu, F, two_mu, T1, 2 * (int64_t)n, 1.0, 0.0, ab, s))
     return false;
@@ -330,7 +353,7 @@ static bool orbital_fix(const double* dAbar, int n_mu, const T* F, const T* Xmu,
   return launch_ok();
 }
 
-template <class T, class TS, class TT>
+template <int PREC, class TS, class TT>
 static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                    bool aliased, const int32_t* idx, int n_mu, const double* minv, const TT* tbar, int64_t ld_tbar,
                    const double* g, TS* dphi, int64_t ld_dphi, TS* dpsi, int64_t ld_dpsi, double* loss,
@@ -338,6 +361,7 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   const int n1 = aliased ? n_mu : 2 * n_mu;
   const int* ab = &P.st->abort;
+  typedef typename Prec<PREC>::E T;
   hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
   T *Ephi = (T*)P.Ephi, *Fphi = (T*)P.Fphi, *Xphi = (T*)P.Xphi;
   T *Epsi = aliased ? Ephi : (T*)P.Epsi, *Fpsi = aliased ? Fphi : (T*)P.Fpsi, *Xpsi = aliased ? Xphi : (T*)P.Xpsi;
@@ -354,6 +378,7 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                        ld_psi, n_psi, idx, n_mu, nr, Xpsi);
   }
   if (!launch_ok()) return ISDF_E_HIP;
+  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
   if (!tbar && !dgemm<KC, KC, double>(n1, n1, n1, minv, n1, minv, n1, P.W2, n1, 1.0, 0.0, 0, ab, s))
     return ISDF_E_HIP;  // (C C^H)^-2
   double* Abar = aliased ? P.A : P.B;  // after the Hadamard step
@@ -361,8 +386,8 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   for (int64_t r = 0; r < nr; r += rblock) {
     const int rows = (int)(nr - r < rblock ? nr - r : rblock);
     // Gram blocks of the r-block: A (and B) kept, G for Theta
-    if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, r, rows, P.G,
-                     n1, aliased ? G_REAL : G_CPLX, ab, s, P.A, aliased ? nullptr : P.B))
+    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, r, rows,
+                        P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, P.A, aliased ? nullptr : P.B))
       return ISDF_E_HIP;
     if (!tbar) {
       // H += G^T diag(g) G (lower tiles, split-K, fixed-order reduction)
@@ -399,10 +424,18 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                          P.A, P.B, (int64_t)rows, n_mu, aliased ? 1 : 0);
       if (!launch_ok()) return ISDF_E_HIP;
     }
-    if (!orbital_block<T, TS>(Abar, n_mu, Fphi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi, P.Qpart, ab, s))
+    if (Prec<PREC>::SPLIT == SPLIT_FP16X3) {  // binary16 scales of Abar, Phi, Bbar, Psi
+      if (!fill<double>(P.amax + 2, 2, 0.0, s)) return ISDF_E_HIP;
+      if (!absmax<double>(Abar, n_mu, n_mu, rows, P.amax + 2, s)) return ISDF_E_HIP;
+      if (!aliased && !absmax<double>(Bbar, n_mu, n_mu, rows, P.amax + 3, s)) return ISDF_E_HIP;
+      hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 4, 2, 0, 3,
+                         aliased ? 0 : 1);
+    }
+    if (!orbital_block<PREC, TS>(Abar, n_mu, Fphi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi, P.Qpart,
+                                 P.sc + 4, ab, s))
       return ISDF_E_HIP;
-    if (!aliased &&
-        !orbital_block<T, TS>(Bbar, n_mu, Fpsi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows, P.Qpsi, P.Qpart, ab, s))
+    if (!aliased && !orbital_block<PREC, TS>(Bbar, n_mu, Fpsi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows, P.Qpsi,
+                                             P.Qpart, P.sc + 6, ab, s))
       return ISDF_E_HIP;
   }
   if (!tbar) {
@@ -413,14 +446,15 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
     if (!dgemm<KC, XC, double>(n1, n1, n1, minv, n1, P.Ppart, n1, P.P, n1, 2.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
   }
   // Mbar terms at the interpolation rows
-  if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu, nullptr,
-                   n1, G_CPLX, ab, s, P.Amu, aliased ? nullptr : P.Bmu))
+  if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu,
+                      nullptr, n1, G_CPLX, ab, s, P.sc, P.Amu, aliased ? nullptr : P.Bmu))
     return ISDF_E_HIP;
   hipLaunchKernelGGL(mbar_hadamard, dim3(blocks_for((int64_t)n_mu * n_mu)), dim3(256), 0, s, (const double*)P.P,
                      (const double*)P.Amu, (const double*)P.Bmu, P.dA, P.dB, n_mu, aliased ? 1 : 0, ab);
   if (!launch_ok()) return ISDF_E_HIP;
-  if (!orbital_fix<T, TS>(P.dA, n_mu, Fphi, Xphi, n_phi, dphi, ld_dphi, idx, P.Qphi, P.T1, ab, s)) return ISDF_E_HIP;
-  if (!aliased && !orbital_fix<T, TS>(P.dB, n_mu, Fpsi, Xpsi, n_psi, dpsi, ld_dpsi, idx, P.Qpsi, P.T1, ab, s))
+  if (!orbital_fix<PREC, TS>(P.dA, n_mu, Fphi, Xphi, n_phi, dphi, ld_dphi, idx, P.Qphi, P.T1, ab, s))
+    return ISDF_E_HIP;
+  if (!aliased && !orbital_fix<PREC, TS>(P.dB, n_mu, Fpsi, Xpsi, n_psi, dpsi, ld_dpsi, idx, P.Qpsi, P.T1, ab, s))
     return ISDF_E_HIP;
   if (aliased && dpsi != dphi) {
     hipLaunchKernelGGL((copy_rows<TS>), dim3(blocks_for(nr * 2 * n_phi)), dim3(256), 0, s, dpsi, ld_dpsi,
@@ -455,22 +489,27 @@ extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const voi
   if (theta_bar && ld_tbar < n_mu) return ISDF_E_ARG;
   if (ld_dphi < n_phi || ld_dpsi < n_psi) return ISDF_E_ARG;
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
-  if (prec == ISDF_P_BF16X6 || prec == ISDF_P_FP16X3) return ISDF_E_UNSUPPORTED;
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
   if (!aliased && dphi == dpsi) return ISDF_E_ARG;
   if (rblock > nr) rblock = nr;
   BwdPlan P = plan_bwd(ws, ws_bytes, n_mu, n_phi, n_psi, aliased, tsize_of(prec), rblock);
   if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  if (prec == ISDF_P_FP64)
-    return bwd_run<double, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
-                                           aliased, idx, n_mu, minv, (const double*)theta_bar, ld_tbar, g,
-                                           (double*)dphi, ld_dphi, (double*)dpsi, ld_dpsi, loss, rblock, info, P, s);
-  if (dt == ISDF_C128)
-    return bwd_run<float, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
-                                          aliased, idx, n_mu, minv, (const double*)theta_bar, ld_tbar, g,
-                                          (double*)dphi, ld_dphi, (double*)dpsi, ld_dpsi, loss, rblock, info, P, s);
-  return bwd_run<float, float, float>(nr, (const float*)phi, ld_phi, n_phi, (const float*)psi, ld_psi, n_psi, aliased,
-                                      idx, n_mu, minv, (const float*)theta_bar, ld_tbar, g, (float*)dphi, ld_dphi,
-                                      (float*)dpsi, ld_dpsi, loss, rblock, info, P, s);
+#define ISDF_BWD_ARGS(TS)                                                                                        \
+  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, minv, (const TS*)theta_bar, \
+      ld_tbar, g, (TS*)dphi, ld_dphi, (TS*)dpsi, ld_dpsi, loss, rblock, info, P, s
+  if (dt == ISDF_C128) {
+    switch (prec) {
+      case ISDF_P_FP64: return bwd_run<ISDF_P_FP64, double, double>(ISDF_BWD_ARGS(double));
+      case ISDF_P_FP32: return bwd_run<ISDF_P_FP32, double, double>(ISDF_BWD_ARGS(double));
+      case ISDF_P_BF16X6: return bwd_run<ISDF_P_BF16X6, double, double>(ISDF_BWD_ARGS(double));
+      default: return bwd_run<ISDF_P_FP16X3, double, double>(ISDF_BWD_ARGS(double));
+    }
+  }
+  switch (prec) {
+    case ISDF_P_FP32: return bwd_run<ISDF_P_FP32, float, float>(ISDF_BWD_ARGS(float));
+    case ISDF_P_BF16X6: return bwd_run<ISDF_P_BF16X6, float, float>(ISDF_BWD_ARGS(float));
+    default: return bwd_run<ISDF_P_FP16X3, float, float>(ISDF_BWD_ARGS(float));
+  }
+#undef ISDF_BWD_ARGS
 }

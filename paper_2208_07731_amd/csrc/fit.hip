@@ -25,6 +25,8 @@ namespace isdf {
 
 struct FitPlan {
   FitState* st;
+  double* amax;  // [2] max |Phi|, max |Psi|
+  double* sc;    // [4] binary16 operand scales of the Gram blocks
   int* marker;
   void* Ephi;
   void* Epsi;
@@ -40,6 +42,8 @@ static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   const int n1 = aliased ? n_mu : 2 * n_mu;
   P.st = c.take<FitState>(1);
+  P.amax = c.take<double>(2);
+  P.sc = c.take<double>(4);
   P.marker = c.take<int>(nr);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
   P.Epsi = aliased ? nullptr : c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize);
@@ -50,7 +54,7 @@ static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   return P;
 }
 
-template <class T, class TS, class TT>
+template <int PREC, class TS, class TT>
 static int fit_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                    bool aliased, const int32_t* idx, int n_mu, double* minv, uint32_t flags, int64_t row0,
                    int64_t nrows, TT* theta, int64_t ld_theta, int64_t rblock, isdf_fit_info* info,
@@ -58,27 +62,29 @@ static int fit_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   const int n1 = aliased ? n_mu : 2 * n_mu;
   const int* ab = &P.st->abort;
+  typedef typename Prec<PREC>::E T;
   hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
   if (!launch_ok()) return ISDF_E_HIP;
   T* Ephi = (T*)P.Ephi;
   T* Epsi = aliased ? Ephi : (T*)P.Epsi;
   if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
   if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
+  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
   if (flags & ISDF_FIT_FACTOR) {
     if (!fill<int>(P.marker, nr, 0, s)) return ISDF_E_HIP;
     hipLaunchKernelGGL(check_idx, dim3((unsigned)ceil_div(n_mu, 256)), dim3(256), 0, s, idx, n_mu, nr, P.marker,
                        P.st);
     if (!launch_ok()) return ISDF_E_HIP;
     // M = C C^H: the Gram + Hadamard of the interpolation rows themselves
-    if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu, minv,
-                     n1, aliased ? G_REAL : G_EMB, ab, s))
+    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu, minv,
+                        n1, aliased ? G_REAL : G_EMB, ab, s, P.sc))
       return ISDF_E_HIP;
     ISDF_TRY(spd_inverse(minv, n1, P.inv, P.st, s));
   }
   for (int64_t r = 0; r < nrows; r += rblock) {
     const int rows = (int)(nrows - r < rblock ? nrows - r : rblock);
-    if (!gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, row0 + r,
-                     rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s))
+    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, row0 + r,
+                        rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc))
       return ISDF_E_HIP;
     const int64_t ldt = aliased ? ld_theta : 2 * ld_theta;
     if (!dgemm<KC, KC, TT>(rows, n1, n1, P.G, n1, minv, n1, theta + r * ldt, ldt, 1.0, 0.0, 0, ab, s))
@@ -118,23 +124,27 @@ extern "C" int isdf_fit(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
   if (!minv || !info || (nrows > 0 && !theta) || row0 < 0 || nrows < 0 || row0 + nrows > nr) return ISDF_E_ARG;
   if (ld_theta < n_mu || rblock <= 0) return ISDF_E_ARG;
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
-  if (prec == ISDF_P_BF16X6 || prec == ISDF_P_FP16X3) return ISDF_E_UNSUPPORTED;
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
   FitPlan P = plan_fit(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, tsize_of(prec), rblock);
   if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  if (prec == ISDF_P_FP64) {
-    return fit_run<double, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
-                                           aliased, idx, n_mu, minv, flags, row0, nrows, (double*)theta, ld_theta,
-                                           rblock, info, P, s);
+#define ISDF_FIT_ARGS(TS, TT)                                                                                   \
+  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, minv, flags, row0, nrows, \
+      (TT*)theta, ld_theta, rblock, info, P, s
+  if (dt == ISDF_C128) {
+    switch (prec) {
+      case ISDF_P_FP64: return fit_run<ISDF_P_FP64, double, double>(ISDF_FIT_ARGS(double, double));
+      case ISDF_P_FP32: return fit_run<ISDF_P_FP32, double, double>(ISDF_FIT_ARGS(double, double));
+      case ISDF_P_BF16X6: return fit_run<ISDF_P_BF16X6, double, double>(ISDF_FIT_ARGS(double, double));
+      default: return fit_run<ISDF_P_FP16X3, double, double>(ISDF_FIT_ARGS(double, double));
+    }
   }
-  if (dt == ISDF_C128)
-    return fit_run<float, double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi,
-                                          aliased, idx, n_mu, minv, flags, row0, nrows, (double*)theta, ld_theta,
-                                          rblock, info, P, s);
-  return fit_run<float, float, float>(nr, (const float*)phi, ld_phi, n_phi, (const float*)psi, ld_psi, n_psi,
-                                      aliased, idx, n_mu, minv, flags, row0, nrows, (float*)theta, ld_theta, rblock,
-                                      info, P, s);
+  switch (prec) {
+    case ISDF_P_FP32: return fit_run<ISDF_P_FP32, float, float>(ISDF_FIT_ARGS(float, float));
+    case ISDF_P_BF16X6: return fit_run<ISDF_P_BF16X6, float, float>(ISDF_FIT_ARGS(float, float));
+    default: return fit_run<ISDF_P_FP16X3, float, float>(ISDF_FIT_ARGS(float, float));
+  }
+#undef ISDF_FIT_ARGS
 }
 
 extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec) {
@@ -142,26 +152,32 @@ extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, 
   Carver c(nullptr, 0);
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   c.take<int>(64);  // abort flag
+  c.take<double>(2);
+  c.take<double>(4);
   c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize_of(prec));
   if (!aliased) c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize_of(prec));
   return c.used;
 }
 
-template <class T, class TS>
+template <int PREC, class TS>
 static int zc_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                   bool aliased, const int32_t* idx, int n_mu, int64_t row0, int64_t nrows, double* G, int64_t ldg,
                   void* ws, size_t cap, hipStream_t s) {
+  typedef typename Prec<PREC>::E T;
   Carver c(ws, cap);
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   int* ab = c.take<int>(64);
+  double* amax = c.take<double>(2);
+  double* sc = c.take<double>(4);
   T* Ephi = c.take<T>((size_t)2 * nmu16 * 2 * n_phi);
   T* Epsi = aliased ? Ephi : c.take<T>((size_t)2 * nmu16 * 2 * n_psi);
   if (!c.fits() || !ws) return ISDF_E_WORKSPACE;
   if (!fill<int>(ab, 1, 0, s)) return ISDF_E_HIP;
   if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
   if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
-  if (nrows > 0 && !gram<T, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr,
-                                row0, (int)nrows, G, ldg, aliased ? G_REAL : G_CPLX, ab, s))
+  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, amax, sc, s)) return ISDF_E_HIP;
+  if (nrows > 0 && !gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr,
+                                   row0, (int)nrows, G, ldg, aliased ? G_REAL : G_CPLX, ab, s, sc))
     return ISDF_E_HIP;
   return ISDF_OK;
 }
@@ -176,16 +192,24 @@ extern "C" int isdf_zc(const isdf_grid* grid, isdf_dtype dt, const void* phi, in
   if (row0 < 0 || nrows < 0 || row0 + nrows > nr || nrows > INT32_MAX || (nrows > 0 && !G)) return ISDF_E_ARG;
   if (ldg < (aliased ? n_mu : 2 * (int64_t)n_mu)) return ISDF_E_ARG;
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
-  if (prec == ISDF_P_BF16X6 || prec == ISDF_P_FP16X3) return ISDF_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
-  if (prec == ISDF_P_FP64)
-    return zc_run<double, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi, aliased,
-                                  idx, n_mu, row0, nrows, G, ldg, ws, ws_bytes, s);
-  if (dt == ISDF_C128)
-    return zc_run<float, double>(nr, (const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi, aliased,
-                                 idx, n_mu, row0, nrows, G, ldg, ws, ws_bytes, s);
-  return zc_run<float, float>(nr, (const float*)phi, ld_phi, n_phi, (const float*)psi, ld_psi, n_psi, aliased, idx,
-                              n_mu, row0, nrows, G, ldg, ws, ws_bytes, s);
+#define ISDF_ZC_ARGS(TS)                                                                                         \
+  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, row0, nrows, G, ldg, ws, \
+      ws_bytes, s
+  if (dt == ISDF_C128) {
+    switch (prec) {
+      case ISDF_P_FP64: return zc_run<ISDF_P_FP64, double>(ISDF_ZC_ARGS(double));
+      case ISDF_P_FP32: return zc_run<ISDF_P_FP32, double>(ISDF_ZC_ARGS(double));
+      case ISDF_P_BF16X6: return zc_run<ISDF_P_BF16X6, double>(ISDF_ZC_ARGS(double));
+      default: return zc_run<ISDF_P_FP16X3, double>(ISDF_ZC_ARGS(double));
+    }
+  }
+  switch (prec) {
+    case ISDF_P_FP32: return zc_run<ISDF_P_FP32, float>(ISDF_ZC_ARGS(float));
+    case ISDF_P_BF16X6: return zc_run<ISDF_P_BF16X6, float>(ISDF_ZC_ARGS(float));
+    default: return zc_run<ISDF_P_FP16X3, float>(ISDF_ZC_ARGS(float));
+  }
+#undef ISDF_ZC_ARGS
 }
 
 extern "C" int isdf_apply_minv(int32_t n_mu, int32_t aliased, const double* minv, const double* G, int64_t ldg,

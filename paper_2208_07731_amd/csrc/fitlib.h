@@ -6,7 +6,7 @@
 #include <float.h>
 #include <limits.h>
 
-#include "gemm.h"
+#include "gemm_split.h"
 
 namespace isdf {
 namespace {
@@ -341,24 +341,125 @@ static int spd_inverse(double* X, int n, InvWork w, FitState* st, hipStream_t s)
   return ISDF_OK;
 }
 
+// Precision policy of the orbital contractions (the Gram blocks and the
+// adjoint's products with Phi_mu / Phi).  E: storage of packed right-hand
+// sides, and compute type of the plain engines; Q: compute type of the
+// split-K reductions over grid rows; SPLIT: split engine or -1.
+template <int PREC>
+struct Prec;
+template <>
+struct Prec<ISDF_P_FP64> {
+  typedef double E;
+  typedef double Q;
+  static constexpr int SPLIT = -1;
+};
+template <>
+struct Prec<ISDF_P_FP32> {
+  typedef float E;
+  typedef float Q;
+  static constexpr int SPLIT = -1;
+};
+template <>
+struct Prec<ISDF_P_BF16X6> {
+  typedef double E;
+  typedef float Q;
+  static constexpr int SPLIT = SPLIT_BF16X6;
+};
+template <>
+struct Prec<ISDF_P_FP16X3> {
+  typedef double E;
+  typedef float Q;
+  static constexpr int SPLIT = SPLIT_FP16X3;
+};
+
+template <int MODE, int BM, int BN, int WM, int WN, class TA, class TB, int NOPS, class Epi>
+static bool launch_split(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0, Operand<TA> A1, Operand<TB> B1,
+                         int64_t K1, const double* scales, const Epi& epi, const int* abort, hipStream_t st) {
+  if (M <= 0 || N <= 0) return true;
+  GemmShape sh{};
+  sh.M = M;
+  sh.N = N;
+  sh.K = K;
+  sh.kchunk = K;
+  sh.splits = 1;
+  sh.abort = abort;
+  const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
+  hipLaunchKernelGGL((gemm_split_kernel<MODE, BM, BN, WM, WN, TA, TB, NOPS, Epi>), dim3((unsigned)tiles),
+                     dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, scales, epi);
+  return launch_ok();
+}
+
+// Largest |real or imaginary part| of an r-major complex matrix, folded into
+// *out (positive doubles order like their bit patterns).
+template <class TS>
+__global__ void absmax_rows(const TS* __restrict__ x, int64_t ld, int n, int64_t nr, double* out) {
+  double m = 0.0;
+  for (int64_t r = blockIdx.x; r < nr; r += gridDim.x)
+    for (int k = threadIdx.x; k < 2 * n; k += blockDim.x) m = fmax(m, fabs((double)x[2 * r * ld + k]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, ISDF_WAVE));
+  if ((threadIdx.x & 63) == 0 && m > 0.0) atomic_max_pos(out, m);
+}
+
+// scale[i] = 2^e with amax[src[i]] 2^e <= 2^14 (binary16 operands).
+__global__ void pow2_scales(const double* amax, double* scale, int a0, int a1, int a2, int a3) {
+  scale[0] = pow2_scale_for(amax[a0]);
+  scale[1] = pow2_scale_for(amax[a1]);
+  scale[2] = pow2_scale_for(amax[a2]);
+  scale[3] = pow2_scale_for(amax[a3]);
+}
+
+template <class TS>
+static bool absmax(const TS* x, int64_t ld, int n, int64_t nr, double* out, hipStream_t s) {
+  int64_t blocks = nr < 2048 ? nr : 2048;
+  hipLaunchKernelGGL((absmax_rows<TS>), dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, s, x, ld, n, nr, out);
+  return launch_ok();
+}
+
+// Operand scales of the Gram blocks: sc[0..3] = (Phi, E_phi, Psi, E_psi);
+// amax[0], amax[1] receive max |Phi|, max |Psi|.  Only the FP16 split uses
+// them; the other precisions pass null scales.
+template <int PREC, class TS>
+static bool gram_scales(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                        bool aliased, int64_t nr, double* amax, double* sc, hipStream_t s) {
+  if (Prec<PREC>::SPLIT != SPLIT_FP16X3) return true;
+  if (!fill<double>(amax, 2, 0.0, s)) return false;
+  if (!absmax<TS>(phi, ld_phi, n_phi, nr, amax, s)) return false;
+  if (!aliased && !absmax<TS>(psi, ld_psi, n_psi, nr, amax + 1, s)) return false;
+  hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)amax, sc, 0, 0, aliased ? 0 : 1,
+                     aliased ? 0 : 1);
+  return launch_ok();
+}
+
 // Gram + Hadamard of `rows` orbital rows (gathered through `gather` if
-// non-null, else starting at row r0) into G.
-template <class T, class TS>
-static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
-                 bool aliased, const T* Ephi, const T* Epsi, int nmu16, int n_mu, const int* gather, int64_t r0,
-                 int rows, double* G, int64_t ldg, int mode, const int* abort, hipStream_t s,
-                 double* Aout = nullptr, double* Bout = nullptr) {
+// non-null, else starting at row r0) into G (and optionally A, B).
+template <int PREC, class TS>
+static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi, bool aliased,
+                 const typename Prec<PREC>::E* Ephi, const typename Prec<PREC>::E* Epsi, int nmu16, int n_mu,
+                 const int* gather, int64_t r0, int rows, double* G, int64_t ldg, int mode, const int* abort,
+                 hipStream_t s, const double* scales, double* Aout = nullptr, double* Bout = nullptr) {
+  typedef typename Prec<PREC>::E T;
+  constexpr int SPLIT = Prec<PREC>::SPLIT;
   EpiGram epi{G, ldg, rows, n_mu, mode, Aout, Bout, 2 * (int64_t)n_mu};
   const int N = 2 * nmu16;
-  Operand<TS> a0{phi + 2 * r0 * ld_phi, 2 * ld_phi, gather};
-  Operand<T> b0{Ephi, 2 * (int64_t)n_phi, nullptr};
-  if (aliased)
-    return launch_gemm<T, 128, 128, 16, 2, 2, TS, KC, T, KC, 1>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0, 0,
-                                                                 epi, 0, abort, s);
-  Operand<TS> a1{psi + 2 * r0 * ld_psi, 2 * ld_psi, gather};
-  Operand<T> b1{Epsi, 2 * (int64_t)n_psi, nullptr};
-  return launch_gemm<T, 128, 64, 16, 2, 2, TS, KC, T, KC, 2>(rows, N, 2 * (int64_t)n_phi, a0, b0, a1, b1,
-                                                              2 * (int64_t)n_psi, epi, 0, abort, s);
+  Operand<TS> a0{phi + 2 * r0 * ld_phi, 2 * ld_phi, gather, nullptr};
+  Operand<T> b0{Ephi, 2 * (int64_t)n_phi, nullptr, nullptr};
+  Operand<TS> a1{psi + 2 * r0 * ld_psi, 2 * ld_psi, gather, nullptr};
+  Operand<T> b1{Epsi, 2 * (int64_t)n_psi, nullptr, nullptr};
+  if constexpr (SPLIT >= 0) {
+    const double* sc = SPLIT == SPLIT_FP16X3 ? scales : nullptr;
+    if (aliased)
+      return launch_split<SPLIT, 128, 64, 2, 2, TS, T, 1>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0, 0, sc, epi,
+                                                           abort, s);
+    return launch_split<SPLIT, 64, 64, 2, 2, TS, T, 2>(rows, N, 2 * (int64_t)n_phi, a0, b0, a1, b1, 2 * (int64_t)n_psi,
+                                                         sc, epi, abort, s);
+  } else {
+    if (aliased)
+      return launch_gemm<T, 128, 128, 16, 2, 2, TS, KC, T, KC, 1>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0, 0,
+                                                                   epi, 0, abort, s);
+    return launch_gemm<T, 128, 64, 16, 2, 2, TS, KC, T, KC, 2>(rows, N, 2 * (int64_t)n_phi, a0, b0, a1, b1,
+                                                                2 * (int64_t)n_psi, epi, 0, abort, s);
+  }
 }
 
 template <class TS, class T>
@@ -388,7 +489,10 @@ static bool fit_args_ok(const isdf_grid* g, isdf_dtype dt, const void* phi, int6
   return true;
 }
 
-static size_t tsize_of(isdf_prec p) { return p == ISDF_P_FP64 ? sizeof(double) : sizeof(float); }
+// Bytes per element of the packed right-hand sides (E, F) and gathered
+// rows: the FP32 engine stages them in float, every other precision in
+// double (the split engines split them while staging).
+static size_t tsize_of(isdf_prec p) { return p == ISDF_P_FP32 ? sizeof(float) : sizeof(double); }
 
 }  // namespace
 }  // namespace isdf

@@ -90,7 +90,7 @@ def test_kmeans_rejects_bad_arguments(case):
     assert code == (L.E_WORKSPACE if case == "no_ws" else L.E_ARG)
 
 
-@pytest.mark.parametrize("case", ["rows", "ld_theta", "prec_dtype", "null_minv", "flags", "no_ws", "unsupported"])
+@pytest.mark.parametrize("case", ["rows", "ld_theta", "prec_dtype", "null_minv", "flags", "no_ws", "bad_prec"])
 def test_fit_rejects_bad_arguments(case):
     lib = L.load()
     g = L.make_grid(8)
@@ -107,10 +107,9 @@ def test_fit_rejects_bad_arguments(case):
         kw["flags"] = 2
     elif case == "no_ws":
         kw["wsb"] = 16
-    elif case == "unsupported":
-        kw["prec"] = 3
-        kw["dt"] = L.C64
+    elif case == "bad_prec":
+        kw["prec"] = 7
     code = lib.isdf_fit(C.byref(g), kw["dt"], FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, kw["prec"], kw["minv"], kw["flags"],
                         kw["row0"], kw["nrows"], FAKE, kw["ldt"], 512, FAKE, FAKE, kw["wsb"], None)
-    expect = {"no_ws": L.E_WORKSPACE, "unsupported": L.E_UNSUPPORTED}.get(case, L.E_ARG)
+    expect = {"no_ws": L.E_WORKSPACE}.get(case, L.E_ARG)
     assert code == expect

@@ -175,3 +175,33 @@ def test_backward_water64_central_fd():
                 an = dphi[r, c].real if unit == 1.0 else dphi[r, c].imag
                 errs.append(abs(fd - an) / scale)
     assert max(errs) <= 1e-6, max(errs)
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
+def test_backward_split_precision_water8(water8, water8_idx, prec):
+    phi = water8["phi"]
+    g = synth.loss_field(phi.shape[0], 1004)
+    ref = oracle.fit_backward(phi, phi, water8_idx, g=g)
+    phi_t, idx_t = dev(phi), dev(water8_idx.astype(np.int32))
+    _, minv, _ = isdf.fit(phi_t, None, idx_t, prec=prec, nrows=0)
+    dphi, _, loss, _ = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(g), prec=prec, rblock=5000)
+    err = rel(dphi.cpu().numpy(), ref["dphi"])
+    print(f"{prec} dphi rel err {err:.3e}, loss rel err {abs(loss.item() - ref['loss']) / ref['loss']:.3e}")
+    assert err <= 1e-5
+    assert abs(loss.item() - ref["loss"]) <= 1e-6 * ref["loss"]
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
+def test_backward_split_precision_complex(prec):
+    rng, big, idx = tiny(17)
+    phi, psi = big[:, :7], big[:, 7:16]
+    g = rng.uniform(0.5, 1.5, phi.shape[0])
+    ref = oracle.fit_backward(phi, psi, idx, g=g)
+    t = dev(big)
+    _, minv, _ = isdf.fit(t[:, :7], t[:, 7:16], dev(idx), grid=(5, 6, 7), nrows=0, prec=prec)
+    dphi, dpsi, loss, _ = isdf.fit_backward(t[:, :7], t[:, 7:16], dev(idx), minv, g=dev(g), grid=(5, 6, 7),
+                                            rblock=64, prec=prec)
+    kappa = oracle.cc_condition(phi, psi, idx)
+    tol = max(1e-5, 1e-7 * kappa)
+    assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
+    assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol

@@ -181,3 +181,59 @@ def test_minv_ragged_orders(n_mu, aliased):
         Me[1::2, 1::2] = M.real
         M = Me
     assert np.linalg.norm(W @ M.real - np.eye(n1)) <= 1e2 * kappa * EPS * np.sqrt(n1)
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fit_split_precision_water8(water8_fit, prec, dtype):
+    """Split-precision Gram blocks on 16-bit matrix cores, FP64 factorisation
+    and solve: Theta within 1e-6 of the FP64 oracle (c64 storage: of the
+    oracle on the upcast data)."""
+    f = water8_fit
+    phi = f["phi"] if dtype == "c128" else f["phi"].astype(np.complex64)
+    theta, _, info = isdf.fit(dev(phi), None, dev(f["idx"].astype(np.int32)), prec=prec)
+    th = theta.cpu().numpy().astype(np.float64)
+    ref = f["ref"]["theta"].real if dtype == "c128" else \
+        oracle.fit_theta(phi.astype(np.complex128), phi.astype(np.complex128), f["idx"]).real
+    err = rel(th, ref)
+    print(f"{prec} {dtype} theta rel err {err:.3e}")
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "fp16x3", "fp32"])
+def test_fit_split_precision_complex_ragged(prec):
+    big, idx = tiny_complex(15)
+    t = dev(big)
+    theta, _, _ = isdf.fit(t[:, :7], t[:, 7:16], dev(idx), grid=(5, 6, 7), prec=prec)
+    ref = oracle.fit(big[:, :7], big[:, 7:16], idx)
+    kappa = oracle.cc_condition(big[:, :7], big[:, 7:16], idx)
+    err = rel(theta.cpu().numpy(), ref["theta"])
+    print(f"{prec} complex theta rel err {err:.3e} (kappa {kappa:.1e})")
+    assert err <= max(1e-6, 1e-8 * kappa)
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
+def test_zc_split_precision(prec):
+    """Z C^H rows from isdf_zc against the oracle's A . conj(B)."""
+    import ctypes as C
+    from paper_2208_07731_amd import _lib as L
+    rng = np.random.default_rng(16)
+    nr, n_phi, n_psi, n_mu = 300, 40, 33, 70
+    phi = rng.standard_normal((nr, n_phi)) + 1j * rng.standard_normal((nr, n_phi))
+    psi = rng.standard_normal((nr, n_psi)) + 1j * rng.standard_normal((nr, n_psi))
+    idx = rng.choice(nr, n_mu, replace=False).astype(np.int32)
+    lib = L.load()
+    pt, st, it = dev(phi), dev(psi), dev(idx)
+    G = torch.empty(nr, 2 * n_mu, dtype=torch.float64, device="cuda")
+    p = L.PRECS[prec]
+    ws = torch.empty(lib.isdf_zc_workspace(n_mu, n_phi, n_psi, 0, p), dtype=torch.uint8, device="cuda")
+    g = L.make_grid((nr, 1, 1))
+    code = lib.isdf_zc(C.byref(g), 0, pt.data_ptr(), n_phi, n_phi, st.data_ptr(), n_psi, n_psi, it.data_ptr(), n_mu,
+                       p, 0, nr, G.data_ptr(), 2 * n_mu, ws.data_ptr(), ws.numel(),
+                       torch.cuda.current_stream().cuda_stream)
+    assert code == 0
+    torch.cuda.synchronize()
+    A, B = oracle.gram_blocks(phi, psi, idx)
+    ref = oracle.hadamard(A, B)
+    got = G.cpu().numpy().view(np.complex128)
+    assert rel(got, ref) <= 1e-6
