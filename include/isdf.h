@@ -193,9 +193,10 @@ int isdf_fit(const isdf_grid* grid /* host */, isdf_dtype dt,
  * isdf_zc: rows [row0, row0 + nrows) of Z C^H = A .* conj(B) (eq. muRownuCol
  * with eq. muRownuColden), Z never formed.  G is [nrows][ldg] FP64: real
  * (aliased, ldg >= n_mu) or interleaved complex (ldg >= 2 n_mu doubles).
- * Workspace: isdf_zc_workspace bytes.
+ * Workspace: isdf_zc_workspace bytes for calls of up to `nrows` rows.
  */
-size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec);
+size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec,
+                         int64_t nrows);
 int isdf_zc(const isdf_grid* grid /* host */, isdf_dtype dt,
             const void* phi, int64_t ld_phi, int32_t n_phi,
             const void* psi, int64_t ld_psi, int32_t n_psi,

@@ -53,7 +53,7 @@ SIGNATURES = {
     "isdf_fit_backward_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32, C.c_int, _I64]),
     "isdf_fit": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _P, _U32, _I64,
                            _I64, _P, _I64, _I64, _P, _P, _SZ, _P]),
-    "isdf_zc_workspace": (_SZ, [_I32, _I32, _I32, _I32, C.c_int]),
+    "isdf_zc_workspace": (_SZ, [_I32, _I32, _I32, _I32, C.c_int, _I64]),
     "isdf_zc": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _I64, _I64, _P, _I64,
                           _P, _SZ, _P]),
     "isdf_apply_minv": (C.c_int, [_I32, _I32, _P, _P, _I64, _I64, C.c_int, _P, _I64, _P]),

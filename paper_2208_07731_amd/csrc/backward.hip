@@ -253,17 +253,44 @@ static int splits_for(int64_t tiles, int64_t K) {
   return s < 1 ? 1 : s;
 }
 
+// Planes of the adjoint's orbital products dX = Abar F (split precisions):
+// the r-block's Abar (or Bbar) rows and the packed F of each orbital set,
+// all with K = 2 N_mu padded to ldp.
+struct AdjPlanes {
+  void* abar;   // [NP][rows_cap][ldp]
+  void* f_phi;  // [NP][2 n_phi][ldp]
+  void* f_psi;  // [NP][2 n_psi][ldp]
+  int ldp;
+  int64_t rows_cap;
+};
+
+static AdjPlanes carve_adj(Carver& c, isdf_prec prec, int n_phi, int n_psi, bool aliased, int n_mu,
+                           int64_t rows_cap) {
+  AdjPlanes a{};
+  if (prec != ISDF_P_BF16X6 && prec != ISDF_P_FP16X3) return a;
+  const int np = prec == ISDF_P_BF16X6 ? 3 : 2;
+  a.ldp = ldp_of(n_mu);
+  a.rows_cap = rows_cap;
+  a.abar = c.take<char>(plane_bytes(np, rows_cap, a.ldp));
+  a.f_phi = c.take<char>(plane_bytes(np, 2 * (int64_t)n_phi, a.ldp));
+  a.f_psi = aliased ? a.f_phi : c.take<char>(plane_bytes(np, 2 * (int64_t)n_psi, a.ldp));
+  return a;
+}
+
 struct BwdPlan {
   FitState* st;
   void *Ephi, *Epsi, *Fphi, *Fpsi, *Xphi, *Xpsi;
   double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart, *W2;
   double* amax;  // [4] max |Phi|, |Psi|, |Abar|, |Bbar| (binary16 split)
-  double* sc;    // [8] operand scales: Gram (4), dPhi (2), dPsi (2)
+  double* sc;    // [12] operand scales: Gram (4), dPhi (2), dPsi (2), padding
+  SplitWork sw;  // orbital-row and Gram right-hand-side planes (split precisions)
+  AdjPlanes ap;  // Abar / Bbar and F planes (split precisions)
   size_t bytes;
 };
 
-static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bool aliased, size_t tsize,
+static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bool aliased, isdf_prec prec,
                         int64_t rblock) {
+  const size_t tsize = tsize_of(prec);
   Carver c(ws, cap);
   BwdPlan P{};
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
@@ -271,7 +298,7 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bo
   const int nmax = n_phi > n_psi ? n_phi : n_psi;
   P.st = c.take<FitState>(1);
   P.amax = c.take<double>(4);
-  P.sc = c.take<double>(8);
+  P.sc = c.take<double>(12);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
   P.Fphi = c.take<char>((size_t)2 * n_phi * 2 * n_mu * tsize);
   P.Xphi = c.take<char>((size_t)n_mu * 2 * n_phi * tsize);
@@ -296,36 +323,47 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bo
   if (!aliased) P.dB = c.take<double>((size_t)n_mu * 2 * n_mu);
   P.T1 = c.take<double>((size_t)n_mu * 2 * nmax);
   P.lpart = c.take<double>((size_t)ceil_div(rblock, 128) * ceil_div(n1, 128));
+  P.sw = carve_split(c, prec, n_phi, n_psi, aliased, n_mu, rblock > n_mu ? rblock : n_mu);
+  P.ap = carve_adj(c, prec, n_phi, n_psi, aliased, n_mu, rblock);
   P.bytes = c.used;
   return P;
 }
 
 // dX rows = Abar F (Abar: rows x 2 N_mu real form, F: packed Phi_mu) in the
-// orbital precision; scales = binary16 operand scales (FP16 split only).
+// orbital precision.  Split precisions: Abar is split into planes here, F's
+// planes (fplanes) were split once per call; scales = binary16 operand
+// scales (s_Abar, s_F), FP16 split only.
 template <int PREC, class TS>
-static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec<PREC>::E* F, int n, TS* dX,
-                     int64_t ld_dx, const double* scales, const int* ab, hipStream_t s) {
+static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const void* fplanes,
+                     int n, TS* dX, int64_t ld_dx, const double* scales, const AdjPlanes& ap, const int* ab,
+                     hipStream_t s) {
   typedef typename Prec<PREC>::E T;
   constexpr int SPLIT = Prec<PREC>::SPLIT;
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if constexpr (SPLIT >= 0) {
+    typedef typename SplitT<SPLIT>::P P;
+    const double* sc = SPLIT == SPLIT_FP16X3 ? scales : nullptr;
+    if (!split_rows<SPLIT, double>(Abar, n_mu, n_mu, nullptr, rows, 0, rows, ap.abar, ap.ldp, ap.rows_cap, sc, s))
+      return false;
     EpiStore<TS> epi{dX, 2 * ld_dx, rows, 2 * n, 1.0, 0.0, nullptr, 0, 0};
-    Operand<double> a{Abar, two_mu, nullptr, nullptr};
-    Operand<T> b{F, two_mu, nullptr, nullptr};
-    return launch_split<SPLIT, 128, 64, 2, 2, double, T, 1>(rows, 2 * n, two_mu, a, b, a, b, 0,
-                                                            SPLIT == SPLIT_FP16X3 ? scales : nullptr, epi, ab, s);
+    PlaneOp<P> a{(const P*)ap.abar, ap.ldp, ap.rows_cap * ap.ldp, nullptr};
+    PlaneOp<P> b{(const P*)fplanes, ap.ldp, 2 * (int64_t)n * ap.ldp, nullptr};
+    return launch_split<SPLIT, 128, 64, 2, 2, 1>(rows, 2 * n, ap.ldp, a, b, a, b, 0, sc, epi, ab, s);
   } else {
+    (void)fplanes;
+    (void)ap;
     return tgemm<T, KC, KC>(rows, 2 * n, two_mu, Abar, two_mu, F, two_mu, dX, 2 * ld_dx, 1.0, 0.0, ab, s);
   }
 }
 
 // One orbital set's share of the block: dX rows = Abar F, Q += Abar^T X.
 template <int PREC, class TS>
-static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const TS* X, int64_t ld_x,
-                          int n, TS* dX, int64_t ld_dx, int64_t r, int rows, double* Q, double* Qpart,
-                          const double* scales, const int* ab, hipStream_t s) {
+static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const void* fplanes,
+                          const TS* X, int64_t ld_x, int n, TS* dX, int64_t ld_dx, int64_t r, int rows, double* Q,
+                          double* Qpart, const double* scales, const AdjPlanes& ap, const int* ab, hipStream_t s) {
   const int64_t two_mu = 2 * (int64_t)n_mu;
-  if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, n, dX + 2 * r * ld_dx, ld_dx, scales, ab, s)) return false;
+  if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s))
+    return false;
   const int64_t tiles = ceil_div(two_mu, 128) * ceil_div(2 * n, 128);
   const int sp = splits_for(tiles, rows);
   const int64_t qn = two_mu * 2 * n;
@@ -379,6 +417,18 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   }
   if (!launch_ok()) return ISDF_E_HIP;
   if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
+  if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
+    return ISDF_E_HIP;
+  if constexpr (Prec<PREC>::SPLIT >= 0) {  // F planes, scaled like the orbitals (sc[1], sc[3])
+    constexpr int SPLIT = Prec<PREC>::SPLIT;
+    const double* sc = SPLIT == SPLIT_FP16X3 ? P.sc : nullptr;
+    if (!split_rows<SPLIT, double>((const double*)Fphi, n_mu, n_mu, nullptr, 2 * n_phi, 0, 2 * n_phi, P.ap.f_phi,
+                                   P.ap.ldp, 2 * n_phi, sc ? sc + 1 : nullptr, s))
+      return ISDF_E_HIP;
+    if (!aliased && !split_rows<SPLIT, double>((const double*)Fpsi, n_mu, n_mu, nullptr, 2 * n_psi, 0, 2 * n_psi,
+                                               P.ap.f_psi, P.ap.ldp, 2 * n_psi, sc ? sc + 3 : nullptr, s))
+      return ISDF_E_HIP;
+  }
   if (!tbar && !dgemm<KC, KC, double>(n1, n1, n1, minv, n1, minv, n1, P.W2, n1, 1.0, 0.0, 0, ab, s))
     return ISDF_E_HIP;  // (C C^H)^-2
   double* Abar = aliased ? P.A : P.B;  // after the Hadamard step
@@ -386,8 +436,8 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   for (int64_t r = 0; r < nr; r += rblock) {
     const int rows = (int)(nr - r < rblock ? nr - r : rblock);
     // Gram blocks of the r-block: A (and B) kept, G for Theta
-    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, r, rows,
-                        P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, P.A, aliased ? nullptr : P.B))
+    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr, r,
+                        rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, &P.sw, P.A, aliased ? nullptr : P.B))
       return ISDF_E_HIP;
     if (!tbar) {
       // H += G^T diag(g) G (lower tiles, split-K, fixed-order reduction)
@@ -431,11 +481,11 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 4, 2, 0, 3,
                          aliased ? 0 : 1);
     }
-    if (!orbital_block<PREC, TS>(Abar, n_mu, Fphi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi, P.Qpart,
-                                 P.sc + 4, ab, s))
+    if (!orbital_block<PREC, TS>(Abar, n_mu, Fphi, P.ap.f_phi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi,
+                                 P.Qpart, P.sc + 4, P.ap, ab, s))
       return ISDF_E_HIP;
-    if (!aliased && !orbital_block<PREC, TS>(Bbar, n_mu, Fpsi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows, P.Qpsi,
-                                             P.Qpart, P.sc + 6, ab, s))
+    if (!aliased && !orbital_block<PREC, TS>(Bbar, n_mu, Fpsi, P.ap.f_psi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows,
+                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, ab, s))
       return ISDF_E_HIP;
   }
   if (!tbar) {
@@ -446,8 +496,8 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
     if (!dgemm<KC, XC, double>(n1, n1, n1, minv, n1, P.Ppart, n1, P.P, n1, 2.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
   }
   // Mbar terms at the interpolation rows
-  if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu,
-                      nullptr, n1, G_CPLX, ab, s, P.sc, P.Amu, aliased ? nullptr : P.Bmu))
+  if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, nr, 0, n_mu,
+                      nullptr, n1, G_CPLX, ab, s, P.sc, &P.sw, P.Amu, aliased ? nullptr : P.Bmu))
     return ISDF_E_HIP;
   hipLaunchKernelGGL(mbar_hadamard, dim3(blocks_for((int64_t)n_mu * n_mu)), dim3(256), 0, s, (const double*)P.P,
                      (const double*)P.Amu, (const double*)P.Bmu, P.dA, P.dB, n_mu, aliased ? 1 : 0, ab);
@@ -473,7 +523,7 @@ using namespace isdf;
 extern "C" size_t isdf_fit_backward_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
                                               int32_t aliased, isdf_prec prec, int64_t rblock) {
   if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
-  return plan_bwd(nullptr, 0, n_mu, n_phi, n_psi, aliased != 0, tsize_of(prec), rblock).bytes;
+  return plan_bwd(nullptr, 0, n_mu, n_phi, n_psi, aliased != 0, prec, rblock).bytes;
 }
 
 extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
@@ -492,7 +542,7 @@ extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const voi
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
   if (!aliased && dphi == dpsi) return ISDF_E_ARG;
   if (rblock > nr) rblock = nr;
-  BwdPlan P = plan_bwd(ws, ws_bytes, n_mu, n_phi, n_psi, aliased, tsize_of(prec), rblock);
+  BwdPlan P = plan_bwd(ws, ws_bytes, n_mu, n_phi, n_psi, aliased, prec, rblock);
   if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 #define ISDF_BWD_ARGS(TS)                                                                                        \

@@ -32,11 +32,13 @@ struct FitPlan {
   void* Epsi;
   InvWork inv;
   double* G;
+  SplitWork sw;
   size_t bytes;
 };
 
 static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, int n_psi, bool aliased,
-                        size_t tsize, int64_t rblock) {
+                        isdf_prec prec, int64_t rblock) {
+  const size_t tsize = tsize_of(prec);
   Carver c(ws, cap);
   FitPlan P{};
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
@@ -50,6 +52,7 @@ static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   P.inv.Y = c.take<double>((size_t)n1 * n1);
   P.inv.R = c.take<double>((size_t)n1 * n1);
   P.G = c.take<double>((size_t)rblock * n1);
+  P.sw = carve_split(c, prec, n_phi, n_psi, aliased, n_mu, rblock > n_mu ? rblock : n_mu);
   P.bytes = c.used;
   return P;
 }
@@ -70,21 +73,23 @@ static int fit_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
   if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
   if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
+  if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
+    return ISDF_E_HIP;
   if (flags & ISDF_FIT_FACTOR) {
     if (!fill<int>(P.marker, nr, 0, s)) return ISDF_E_HIP;
     hipLaunchKernelGGL(check_idx, dim3((unsigned)ceil_div(n_mu, 256)), dim3(256), 0, s, idx, n_mu, nr, P.marker,
                        P.st);
     if (!launch_ok()) return ISDF_E_HIP;
     // M = C C^H: the Gram + Hadamard of the interpolation rows themselves
-    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, 0, n_mu, minv,
-                        n1, aliased ? G_REAL : G_EMB, ab, s, P.sc))
+    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, nr, 0, n_mu,
+                        minv, n1, aliased ? G_REAL : G_EMB, ab, s, P.sc, &P.sw))
       return ISDF_E_HIP;
     ISDF_TRY(spd_inverse(minv, n1, P.inv, P.st, s));
   }
   for (int64_t r = 0; r < nrows; r += rblock) {
     const int rows = (int)(nrows - r < rblock ? nrows - r : rblock);
-    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, row0 + r,
-                        rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc))
+    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr,
+                        row0 + r, rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, &P.sw))
       return ISDF_E_HIP;
     const int64_t ldt = aliased ? ld_theta : 2 * ld_theta;
     if (!dgemm<KC, KC, TT>(rows, n1, n1, P.G, n1, minv, n1, theta + r * ldt, ldt, 1.0, 0.0, 0, ab, s))
@@ -110,7 +115,7 @@ extern "C" size_t isdf_fit_workspace(const isdf_grid* grid, int32_t n_mu, int32_
   if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
   const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   if (nr <= 0) return 0;
-  return plan_fit(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, tsize_of(prec), rblock).bytes;
+  return plan_fit(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, prec, rblock).bytes;
 }
 
 extern "C" int isdf_fit(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
@@ -125,7 +130,7 @@ extern "C" int isdf_fit(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
   if (ld_theta < n_mu || rblock <= 0) return ISDF_E_ARG;
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
-  FitPlan P = plan_fit(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, tsize_of(prec), rblock);
+  FitPlan P = plan_fit(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, prec, rblock);
   if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 #define ISDF_FIT_ARGS(TS, TT)                                                                                   \
@@ -147,37 +152,54 @@ extern "C" int isdf_fit(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
 #undef ISDF_FIT_ARGS
 }
 
-extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec) {
-  if (n_mu <= 0 || n_phi <= 0 || n_psi <= 0) return 0;
-  Carver c(nullptr, 0);
+// Workspace layout of isdf_zc (the size query and the call share it).
+struct ZcPlan {
+  int* ab;
+  double* amax;
+  double* sc;
+  void* Ephi;
+  void* Epsi;
+  SplitWork sw;
+  size_t bytes;
+};
+
+static ZcPlan plan_zc(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bool aliased, isdf_prec prec,
+                      int64_t nrows) {
+  Carver c(ws, cap);
+  ZcPlan P{};
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
-  c.take<int>(64);  // abort flag
-  c.take<double>(2);
-  c.take<double>(4);
-  c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize_of(prec));
-  if (!aliased) c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize_of(prec));
-  return c.used;
+  P.ab = c.take<int>(64);
+  P.amax = c.take<double>(2);
+  P.sc = c.take<double>(4);
+  P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize_of(prec));
+  P.Epsi = aliased ? P.Ephi : c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize_of(prec));
+  P.sw = carve_split(c, prec, n_phi, n_psi, aliased, n_mu, nrows > 0 ? nrows : 1);
+  P.bytes = c.used;
+  return P;
+}
+
+extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec,
+                                    int64_t nrows) {
+  if (n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || nrows < 0) return 0;
+  return plan_zc(nullptr, 0, n_mu, n_phi, n_psi, aliased != 0, prec, nrows).bytes;
 }
 
 template <int PREC, class TS>
 static int zc_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                   bool aliased, const int32_t* idx, int n_mu, int64_t row0, int64_t nrows, double* G, int64_t ldg,
-                  void* ws, size_t cap, hipStream_t s) {
+                  const ZcPlan& P, hipStream_t s) {
   typedef typename Prec<PREC>::E T;
-  Carver c(ws, cap);
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
-  int* ab = c.take<int>(64);
-  double* amax = c.take<double>(2);
-  double* sc = c.take<double>(4);
-  T* Ephi = c.take<T>((size_t)2 * nmu16 * 2 * n_phi);
-  T* Epsi = aliased ? Ephi : c.take<T>((size_t)2 * nmu16 * 2 * n_psi);
-  if (!c.fits() || !ws) return ISDF_E_WORKSPACE;
-  if (!fill<int>(ab, 1, 0, s)) return ISDF_E_HIP;
+  T* Ephi = (T*)P.Ephi;
+  T* Epsi = (T*)P.Epsi;
+  if (!fill<int>(P.ab, 1, 0, s)) return ISDF_E_HIP;
   if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
   if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
-  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, amax, sc, s)) return ISDF_E_HIP;
+  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
+  if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
+    return ISDF_E_HIP;
   if (nrows > 0 && !gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr,
-                                   row0, (int)nrows, G, ldg, aliased ? G_REAL : G_CPLX, ab, s, sc))
+                                   nr, row0, (int)nrows, G, ldg, aliased ? G_REAL : G_CPLX, P.ab, s, P.sc, &P.sw))
     return ISDF_E_HIP;
   return ISDF_OK;
 }
@@ -192,10 +214,11 @@ extern "C" int isdf_zc(const isdf_grid* grid, isdf_dtype dt, const void* phi, in
   if (row0 < 0 || nrows < 0 || row0 + nrows > nr || nrows > INT32_MAX || (nrows > 0 && !G)) return ISDF_E_ARG;
   if (ldg < (aliased ? n_mu : 2 * (int64_t)n_mu)) return ISDF_E_ARG;
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
+  ZcPlan P = plan_zc(ws, ws_bytes, n_mu, n_phi, n_psi, aliased, prec, nrows);
+  if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-#define ISDF_ZC_ARGS(TS)                                                                                         \
-  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, row0, nrows, G, ldg, ws, \
-      ws_bytes, s
+#define ISDF_ZC_ARGS(TS) \
+  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, row0, nrows, G, ldg, P, s
   if (dt == ISDF_C128) {
     switch (prec) {
       case ISDF_P_FP64: return zc_run<ISDF_P_FP64, double>(ISDF_ZC_ARGS(double));

@@ -372,9 +372,11 @@ struct Prec<ISDF_P_FP16X3> {
   static constexpr int SPLIT = SPLIT_FP16X3;
 };
 
-template <int MODE, int BM, int BN, int WM, int WN, class TA, class TB, int NOPS, class Epi>
-static bool launch_split(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0, Operand<TA> A1, Operand<TB> B1,
-                         int64_t K1, const double* scales, const Epi& epi, const int* abort, hipStream_t st) {
+template <int MODE, int BM, int BN, int WM, int WN, int NOPS, class Epi>
+static bool launch_split(int M, int N, int64_t K, PlaneOp<typename SplitT<MODE>::P> A0,
+                         PlaneOp<typename SplitT<MODE>::P> B0, PlaneOp<typename SplitT<MODE>::P> A1,
+                         PlaneOp<typename SplitT<MODE>::P> B1, int64_t K1, const double* scales, const Epi& epi,
+                         const int* abort, hipStream_t st) {
   if (M <= 0 || N <= 0) return true;
   GemmShape sh{};
   sh.M = M;
@@ -384,8 +386,34 @@ static bool launch_split(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0
   sh.splits = 1;
   sh.abort = abort;
   const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
-  hipLaunchKernelGGL((gemm_split_kernel<MODE, BM, BN, WM, WN, TA, TB, NOPS, Epi>), dim3((unsigned)tiles),
+  hipLaunchKernelGGL((gemm_split_kernel<MODE, BM, BN, WM, WN, NOPS, Epi>), dim3((unsigned)tiles),
                      dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, scales, epi);
+  return launch_ok();
+}
+
+// Plane buffers of the split engines (16-bit parts, K padded to 32).
+struct SplitWork {
+  void* rows_a;      // parts of orbital rows of Phi  [NP][rows_cap][ldp_a]
+  void* rows_b;      //                     of Psi    [NP][rows_cap][ldp_b]
+  void* e_a;         // parts of the packed Gram right-hand side of Phi [NP][e_rows][ldp_a]
+  void* e_b;         //                                          of Psi
+  int ldp_a, ldp_b;  // 2 n rounded up to 32
+  int64_t rows_cap;
+  int e_rows;        // 2 N_mu rounded up to 32
+};
+
+static inline int ldp_of(int n) { return (int)ceil_div(2 * (int64_t)n, 32) * 32; }
+static inline size_t plane_bytes(int np, int64_t rows, int ldp) { return (size_t)np * rows * ldp * 2; }
+
+template <int MODE, class TS>
+static bool split_rows(const TS* x, int64_t ld, int n, const int* gather, int64_t nr_src, int64_t r0, int rows,
+                       void* out, int ldp, int64_t rows_cap, const double* scale, hipStream_t s) {
+  if (rows <= 0) return true;
+  const int64_t work = (int64_t)rows * (ldp / 8);
+  int64_t blocks = ceil_div(work, 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL((split_planes<MODE, TS>), dim3((unsigned)blocks), dim3(256), 0, s, x, ld, n, gather, nr_src, r0,
+                     rows, (typename SplitT<MODE>::P*)out, ldp, rows_cap * ldp, scale);
   return launch_ok();
 }
 
@@ -436,8 +464,9 @@ static bool gram_scales(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi,
 template <int PREC, class TS>
 static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi, bool aliased,
                  const typename Prec<PREC>::E* Ephi, const typename Prec<PREC>::E* Epsi, int nmu16, int n_mu,
-                 const int* gather, int64_t r0, int rows, double* G, int64_t ldg, int mode, const int* abort,
-                 hipStream_t s, const double* scales, double* Aout = nullptr, double* Bout = nullptr) {
+                 const int* gather, int64_t nr, int64_t r0, int rows, double* G, int64_t ldg, int mode,
+                 const int* abort, hipStream_t s, const double* scales, const SplitWork* sw, double* Aout = nullptr,
+                 double* Bout = nullptr) {
   typedef typename Prec<PREC>::E T;
   constexpr int SPLIT = Prec<PREC>::SPLIT;
   EpiGram epi{G, ldg, rows, n_mu, mode, Aout, Bout, 2 * (int64_t)n_mu};
@@ -447,12 +476,21 @@ static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_
   Operand<TS> a1{psi + 2 * r0 * ld_psi, 2 * ld_psi, gather, nullptr};
   Operand<T> b1{Epsi, 2 * (int64_t)n_psi, nullptr, nullptr};
   if constexpr (SPLIT >= 0) {
+    typedef typename SplitT<SPLIT>::P P;
     const double* sc = SPLIT == SPLIT_FP16X3 ? scales : nullptr;
+    if (!split_rows<SPLIT, TS>(phi, ld_phi, n_phi, gather, nr, gather ? 0 : r0, rows, sw->rows_a, sw->ldp_a,
+                               sw->rows_cap, sc, s))
+      return false;
+    PlaneOp<P> pa0{(const P*)sw->rows_a, sw->ldp_a, sw->rows_cap * sw->ldp_a, nullptr};
+    PlaneOp<P> pb0{(const P*)sw->e_a, sw->ldp_a, (int64_t)sw->e_rows * sw->ldp_a, nullptr};
     if (aliased)
-      return launch_split<SPLIT, 128, 64, 2, 2, TS, T, 1>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0, 0, sc, epi,
-                                                           abort, s);
-    return launch_split<SPLIT, 64, 64, 2, 2, TS, T, 2>(rows, N, 2 * (int64_t)n_phi, a0, b0, a1, b1, 2 * (int64_t)n_psi,
-                                                         sc, epi, abort, s);
+      return launch_split<SPLIT, 128, 64, 2, 2, 1>(rows, N, sw->ldp_a, pa0, pb0, pa0, pb0, 0, sc, epi, abort, s);
+    if (!split_rows<SPLIT, TS>(psi, ld_psi, n_psi, gather, nr, gather ? 0 : r0, rows, sw->rows_b, sw->ldp_b,
+                               sw->rows_cap, sc ? sc + 2 : nullptr, s))
+      return false;
+    PlaneOp<P> pa1{(const P*)sw->rows_b, sw->ldp_b, sw->rows_cap * sw->ldp_b, nullptr};
+    PlaneOp<P> pb1{(const P*)sw->e_b, sw->ldp_b, (int64_t)sw->e_rows * sw->ldp_b, nullptr};
+    return launch_split<SPLIT, 64, 64, 2, 2, 2>(rows, N, sw->ldp_a, pa0, pb0, pa1, pb1, sw->ldp_b, sc, epi, abort, s);
   } else {
     if (aliased)
       return launch_gemm<T, 128, 128, 16, 2, 2, TS, KC, T, KC, 1>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0, 0,
@@ -471,6 +509,42 @@ static bool pack(const TS* phi, int64_t ld, int n, const int* idx, int n_mu, int
   hipLaunchKernelGGL((pack_gram_rhs<TS, T>), dim3((unsigned)blocks), dim3(256), 0, s, phi, ld, n, idx, n_mu, nr,
                      2 * nmu16, E);
   return launch_ok();
+}
+
+// Parts of the packed Gram right-hand sides (split precisions only).
+template <int PREC>
+static bool split_rhs(const double* Ephi, const double* Epsi, int n_phi, int n_psi, bool aliased,
+                      const double* scales, const SplitWork* sw, hipStream_t s) {
+  constexpr int SPLIT = Prec<PREC>::SPLIT;
+  if constexpr (SPLIT >= 0) {
+    const double* sc = SPLIT == SPLIT_FP16X3 ? scales : nullptr;
+    if (!split_rows<SPLIT, double>(Ephi, n_phi, n_phi, nullptr, sw->e_rows, 0, sw->e_rows, sw->e_a, sw->ldp_a,
+                                   sw->e_rows, sc ? sc + 1 : nullptr, s))
+      return false;
+    if (!aliased && !split_rows<SPLIT, double>(Epsi, n_psi, n_psi, nullptr, sw->e_rows, 0, sw->e_rows, sw->e_b,
+                                               sw->ldp_b, sw->e_rows, sc ? sc + 3 : nullptr, s))
+      return false;
+  }
+  return true;
+}
+
+// Carves the plane buffers of a split precision (no-op otherwise).
+static SplitWork carve_split(Carver& c, isdf_prec prec, int n_phi, int n_psi, bool aliased, int n_mu,
+                             int64_t rows_cap) {
+  SplitWork w{};
+  if (prec != ISDF_P_BF16X6 && prec != ISDF_P_FP16X3) return w;
+  const int np = prec == ISDF_P_BF16X6 ? 3 : 2;
+  w.ldp_a = ldp_of(n_phi);
+  w.ldp_b = ldp_of(n_psi);
+  w.rows_cap = rows_cap;
+  w.e_rows = (int)ceil_div(2 * (int64_t)ceil_div(n_mu, 16) * 16, 32) * 32;
+  w.rows_a = c.take<char>(plane_bytes(np, rows_cap, w.ldp_a));
+  w.e_a = c.take<char>(plane_bytes(np, w.e_rows, w.ldp_a));
+  if (!aliased) {
+    w.rows_b = c.take<char>(plane_bytes(np, rows_cap, w.ldp_b));
+    w.e_b = c.take<char>(plane_bytes(np, w.e_rows, w.ldp_b));
+  }
+  return w;
 }
 
 static bool fit_args_ok(const isdf_grid* g, isdf_dtype dt, const void* phi, int64_t ld_phi, int n_phi,

@@ -1,8 +1,10 @@
 // Split-precision MFMA GEMM for gfx950: FP64-accurate-enough products from
 // 16-bit matrix cores.
 //
-//   acc(m, n) = sum_k A(m, k) B(k, n),  A and B given K-contiguous (KC) in
-//   double or float, split while they are staged into LDS:
+//   acc(m, n) = sum_k A(m, k) B(k, n), A and B K-contiguous (KC).
+//
+// The operands are split once, in an HBM pass (split_planes), into planes
+// of 16-bit parts; the GEMM then streams the parts straight into LDS:
 //
 //   BF16X6: x = h + m + l, three bfloat16 parts taken successively from the
 //           exact residuals; products h.h | h.m + m.h + h.l + m.m + l.h
@@ -83,68 +85,63 @@ struct SplitCfg {
   __device__ __forceinline__ static int orow(int lane, int j) { return 4 * (lane >> 4) + j; }
 };
 
-// Stages one BK slice of a KC operand: thread -> (x, E consecutive k),
-// source kept in registers, split into NP part planes [X][LDK] on store.
-template <int MODE, class TS, int X, int THREADS>
-struct SplitStager {
+// An operand already split into NP planes of 16-bit parts: part q of
+// element (x, k) at p[q * pstride + row(x) * ld + k]; ld and the K extent
+// are multiples of 32 (zero-padded), so K needs no guard.
+template <class P>
+struct PlaneOp {
+  const P* p;
+  int64_t ld;
+  int64_t pstride;
+  const int* rows;  // optional gather of x, may be null
+};
+
+// Stages one 32-deep slice of a plane operand: the NP x X x 4 16-byte
+// chunks are spread over the workgroup and copied to LDS [NP][X][LDK].
+template <int MODE, int X, int THREADS>
+struct PlaneStager {
   typedef SplitT<MODE> S;
-  static constexpr int BK = 32;
-  static constexpr int E = X * BK / THREADS;
-  static constexpr int RUNS = BK / E;
-  static_assert(E % 8 == 0, "runs of whole 16-byte parts");
-  double v[E];
-  __device__ __forceinline__ void load(const Operand<TS>& op, int x0, int xlim, int64_t k0, int64_t klim, int tid,
-                                       int64_t row, bool aligned) {
-    const int x = tid / RUNS;
-    const int64_t kb = k0 + (tid % RUNS) * E;
-    const TS* base = op.p + row * op.ld + kb;
-    if (aligned && x0 + X <= xlim && k0 + BK <= klim) {
+  typedef typename S::V V;
+  static constexpr int CHUNKS = S::NP * X * 4;
+  static constexpr int PER = (CHUNKS + THREADS - 1) / THREADS;
+  V v[PER];
+  int64_t off[PER];  // element offset of each chunk's row start (without k)
+  __device__ __forceinline__ void init(const PlaneOp<typename S::P>& op, int x0, int xlim, int tid) {
 #pragma unroll
-      for (int e = 0; e < E; e += 2) load_pair<TS>(base + e, v[e], v[e + 1]);
-    } else {
-      const bool okx = x0 + x < xlim;
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = (okx && kb + e < klim) ? (double)base[e] : 0.0;
+    for (int c = 0; c < PER; ++c) {
+      const int id = tid + c * THREADS;
+      const int q = id / (X * 4), rem = id % (X * 4), x = rem / 4;
+      int xr = x0 + x;
+      xr = xr < xlim ? xr : (xlim > 0 ? xlim - 1 : 0);  // rows past the edge: any valid row
+      const int64_t row = op.rows ? (int64_t)op.rows[xr] : (int64_t)xr;
+      off[c] = q * op.pstride + row * op.ld + 8 * (rem % 4);
     }
   }
-  __device__ __forceinline__ void store(typename S::P* s, int lds_k, int tid, double scale) const {
-    const int x = tid / RUNS, kb = (tid % RUNS) * E;
-    typename S::P parts[S::NP][E];
+  __device__ __forceinline__ void load(const PlaneOp<typename S::P>& op, int64_t k0, int tid) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      typename S::P o[S::NP];
-      S::split(v[e], scale, o);
+    for (int c = 0; c < PER; ++c)
+      if (CHUNKS % THREADS == 0 || tid + c * THREADS < CHUNKS)
+        v[c] = *reinterpret_cast<const V*>(op.p + off[c] + k0);
+  }
+  __device__ __forceinline__ void store(typename S::P* s, int lds_k, int tid) const {
 #pragma unroll
-      for (int p = 0; p < S::NP; ++p) parts[p][e] = o[p];
-    }
-#pragma unroll
-    for (int p = 0; p < S::NP; ++p) {
-      typename S::V* d = reinterpret_cast<typename S::V*>(s + (p * X + x) * lds_k + kb);
-#pragma unroll
-      for (int q = 0; q < E / 8; ++q) {
-        typename S::V w;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) w[e] = parts[p][8 * q + e];
-        d[q] = w;
+    for (int c = 0; c < PER; ++c) {
+      const int id = tid + c * THREADS;
+      if (CHUNKS % THREADS == 0 || id < CHUNKS) {
+        const int q = id / (X * 4), rem = id % (X * 4);
+        *reinterpret_cast<V*>(s + (q * X + rem / 4) * lds_k + 8 * (rem % 4)) = v[c];
       }
     }
-  }
-  __device__ __forceinline__ static int64_t row_of(const Operand<TS>& op, int x0, int xlim, int tid) {
-    const int x = x0 + tid / RUNS;
-    const int xc = x < xlim ? x : (xlim > 0 ? xlim - 1 : 0);
-    return op.rows ? (int64_t)op.rows[xc] : (int64_t)xc;
-  }
-  __device__ __forceinline__ static bool aligned(const Operand<TS>& op) {
-    return (op.ld % 2 == 0) && (((uintptr_t)op.p) % (2 * sizeof(TS)) == 0);
   }
 };
 
 // K loop of one operand pair into the leading (acc0) and correction (acc1)
 // accumulators.  Single LDS buffer, the next slice prefetched in registers.
-template <int MODE, class Cfg, class TA, class TB, int BM, int BN>
-__device__ __forceinline__ void split_loop(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M, int N,
-                                           int64_t K, double sa, double sb, typename SplitT<MODE>::P* smem,
-                                           f4v (&acc0)[Cfg::MI][Cfg::NI], f4v (&acc1)[Cfg::MI][Cfg::NI]) {
+template <int MODE, class Cfg, int BM, int BN>
+__device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::P>& A,
+                                           const PlaneOp<typename SplitT<MODE>::P>& B, int m0, int n0, int M, int N,
+                                           int64_t K, typename SplitT<MODE>::P* smem, f4v (&acc0)[Cfg::MI][Cfg::NI],
+                                           f4v (&acc1)[Cfg::MI][Cfg::NI]) {
   typedef SplitT<MODE> S;
   typedef typename S::P P;
   typedef typename S::V V;
@@ -153,24 +150,22 @@ __device__ __forceinline__ void split_loop(const Operand<TA>& A, const Operand<T
   P* Bs = smem + S::NP * BM * LDK;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv / (BN / Cfg::WTN), wn = wv % (BN / Cfg::WTN);
-  typedef SplitStager<MODE, TA, BM, Cfg::THREADS> SA;
-  typedef SplitStager<MODE, TB, BN, Cfg::THREADS> SB;
-  SA sa_;
-  SB sb_;
-  const int64_t rowa = SA::row_of(A, m0, M, tid), rowb = SB::row_of(B, n0, N, tid);
-  const bool ala = SA::aligned(A), alb = SB::aligned(B);
+  PlaneStager<MODE, BM, Cfg::THREADS> sa;
+  PlaneStager<MODE, BN, Cfg::THREADS> sb;
+  sa.init(A, m0, M, tid);
+  sb.init(B, n0, N, tid);
   if (K <= 0) return;
-  sa_.load(A, m0, M, 0, K, tid, rowa, ala);
-  sb_.load(B, n0, N, 0, K, tid, rowb, alb);
-  sa_.store(As, LDK, tid, sa);
-  sb_.store(Bs, LDK, tid, sb);
+  sa.load(A, 0, tid);
+  sb.load(B, 0, tid);
+  sa.store(As, LDK, tid);
+  sb.store(Bs, LDK, tid);
   __syncthreads();
   const int q8 = 8 * (lane >> 4);
   for (int64_t k0 = 0; k0 < K; k0 += Cfg::BK) {
     const bool more = k0 + Cfg::BK < K;
     if (more) {
-      sa_.load(A, m0, M, k0 + Cfg::BK, K, tid, rowa, ala);
-      sb_.load(B, n0, N, k0 + Cfg::BK, K, tid, rowb, alb);
+      sa.load(A, k0 + Cfg::BK, tid);
+      sb.load(B, k0 + Cfg::BK, tid);
     }
     V a[S::NP][Cfg::MI], b[S::NP][Cfg::NI];
 #pragma unroll
@@ -194,10 +189,43 @@ __device__ __forceinline__ void split_loop(const Operand<TA>& A, const Operand<T
       for (int j = 0; j < Cfg::NI; ++j) S::mma(a[0][i], b[0][j], acc0[i][j]);
     __syncthreads();
     if (more) {
-      sa_.store(As, LDK, tid, sa);
-      sb_.store(Bs, LDK, tid, sb);
+      sa.store(As, LDK, tid);
+      sb.store(Bs, LDK, tid);
       __syncthreads();
     }
+  }
+}
+
+// Split of rows of an r-major complex matrix (or a real matrix read as
+// one) into planes [NP][rows][ldp] of 16-bit parts; columns 2n .. ldp-1 are
+// zero.  `gather` (optional) lists the source rows; scale (optional, device)
+// multiplies before the split (binary16).
+template <int MODE, class TS>
+__global__ void split_planes(const TS* __restrict__ x, int64_t ld, int n, const int* __restrict__ gather,
+                             int64_t nr_src, int64_t r0, int rows, typename SplitT<MODE>::P* __restrict__ out,
+                             int ldp, int64_t pstride, const double* scale) {
+  typedef SplitT<MODE> S;
+  const double s = scale ? *scale : 1.0;
+  const int cpr = ldp / 8;  // 8-element chunks per row
+  const int64_t total = (int64_t)rows * cpr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / cpr), k0 = 8 * (int)(e % cpr);
+    int64_t src = gather ? (int64_t)gather[r] : r0 + r;
+    if (src < 0 || src >= nr_src) src = 0;  // invalid gathers are reported elsewhere
+    const TS* row = x + 2 * src * ld;
+    typename S::V w[S::NP];
+#pragma unroll
+    for (int e8 = 0; e8 < 8; ++e8) {
+      const int k = k0 + e8;
+      const double v = k < 2 * n ? (double)row[k] : 0.0;
+      typename S::P o[S::NP];
+      S::split(v, s, o);
+#pragma unroll
+      for (int q = 0; q < S::NP; ++q) w[q][e8] = o[q];
+    }
+#pragma unroll
+    for (int q = 0; q < S::NP; ++q)
+      *reinterpret_cast<typename S::V*>(out + q * pstride + (int64_t)r * ldp + k0) = w[q];
   }
 }
 
@@ -212,11 +240,12 @@ __device__ __forceinline__ double pow2_scale_for(double amax) {
 
 // NOPS = 1 or 2 operand pairs (two pairs: two accumulator sets, e.g. the
 // Gram blocks of Phi and Psi for the same tile).  scales: null (BF16X6) or
-// device [s_A0, s_B0, s_A1, s_B1] (FP16X3).
-template <int MODE, int BM, int BN, int WM, int WN, class TA, class TB, int NOPS, class Epi>
-__global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(GemmShape sh, Operand<TA> A0, Operand<TB> B0,
-                                                                       Operand<TA> A1, Operand<TB> B1, int64_t K1,
-                                                                       const double* scales, Epi epi) {
+// device [s_A0, s_B0, s_A1, s_B1] the planes were scaled by (FP16X3).
+template <int MODE, int BM, int BN, int WM, int WN, int NOPS, class Epi>
+__global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
+    GemmShape sh, PlaneOp<typename SplitT<MODE>::P> A0, PlaneOp<typename SplitT<MODE>::P> B0,
+    PlaneOp<typename SplitT<MODE>::P> A1, PlaneOp<typename SplitT<MODE>::P> B1, int64_t K1, const double* scales,
+    Epi epi) {
   typedef SplitCfg<BM, BN, WM, WN> Cfg;
   typedef SplitT<MODE> S;
   if (sh.abort && *sh.abort) return;
@@ -229,12 +258,10 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(GemmSh
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv / (BN / Cfg::WTN), wn = wv % (BN / Cfg::WTN);
   TileAt at{m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, 0, 0};
-  double s0a = 1.0, s0b = 1.0, s1a = 1.0, s1b = 1.0;
+  double u0 = 1.0, u1 = 1.0;
   if (scales) {
-    s0a = scales[0];
-    s0b = scales[1];
-    s1a = scales[2];
-    s1b = scales[3];
+    u0 = 1.0 / (scales[0] * scales[1]);
+    u1 = 1.0 / (scales[2] * scales[3]);
   }
   f4v c0[Cfg::MI][Cfg::NI], c1[Cfg::MI][Cfg::NI];
   d4v r0[Cfg::MI][Cfg::NI];
@@ -242,8 +269,7 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(GemmSh
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
     for (int j = 0; j < Cfg::NI; ++j) c0[i][j] = c1[i][j] = f4v{0, 0, 0, 0};
-  split_loop<MODE, Cfg, TA, TB, BM, BN>(A0, B0, m0, n0, sh.M, sh.N, sh.K, s0a, s0b, smem, c0, c1);
-  const double u0 = 1.0 / (s0a * s0b);
+  split_loop<MODE, Cfg, BM, BN>(A0, B0, m0, n0, sh.M, sh.N, sh.K, smem, c0, c1);
 #pragma unroll
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
@@ -256,9 +282,8 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(GemmSh
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j) c0[i][j] = c1[i][j] = f4v{0, 0, 0, 0};
     __syncthreads();
-    split_loop<MODE, Cfg, TA, TB, BM, BN>(A1, B1, m0, n0, sh.M, sh.N, K1, s1a, s1b, smem, c0, c1);
+    split_loop<MODE, Cfg, BM, BN>(A1, B1, m0, n0, sh.M, sh.N, K1, smem, c0, c1);
     d4v r1[Cfg::MI][Cfg::NI];
-    const double u1 = 1.0 / (s1a * s1b);
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll

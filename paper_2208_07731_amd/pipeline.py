@@ -54,7 +54,7 @@ class ISDFStep:
         self.fit_info = torch.zeros(C.sizeof(L.FitInfo), dtype=u8, device=dev)
         self.fit_ws = torch.empty(self.lib.isdf_fit_workspace(C.byref(self.grid), n_mu, self.npf, self.nps,
                                                               int(self.aliased), self.prec, 1), dtype=u8, device=dev)
-        self.zc_ws = torch.empty(self.lib.isdf_zc_workspace(n_mu, self.npf, self.nps, int(self.aliased), self.prec),
+        self.zc_ws = torch.empty(self.lib.isdf_zc_workspace(n_mu, self.npf, self.nps, int(self.aliased), self.prec, n_r),
                                  dtype=u8, device=dev)
         self.G = torch.empty(n_r, self.n1, dtype=f64, device=dev)
         real_t = f64 if self.dt == L.C128 else torch.float32

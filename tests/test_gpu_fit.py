@@ -226,7 +226,7 @@ def test_zc_split_precision(prec):
     pt, st, it = dev(phi), dev(psi), dev(idx)
     G = torch.empty(nr, 2 * n_mu, dtype=torch.float64, device="cuda")
     p = L.PRECS[prec]
-    ws = torch.empty(lib.isdf_zc_workspace(n_mu, n_phi, n_psi, 0, p), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(lib.isdf_zc_workspace(n_mu, n_phi, n_psi, 0, p, nr), dtype=torch.uint8, device="cuda")
     g = L.make_grid((nr, 1, 1))
     code = lib.isdf_zc(C.byref(g), 0, pt.data_ptr(), n_phi, n_phi, st.data_ptr(), n_psi, n_psi, it.data_ptr(), n_mu,
                        p, 0, nr, G.data_ptr(), 2 * n_mu, ws.data_ptr(), ws.numel(),
