@@ -62,6 +62,51 @@ def read_traffic(workload: str):
         return None
 
 
+MFMA_PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0, "fp16x3": 2500.0}  # TFLOP/s, dense
+ISSUED = {"fp64": 1, "fp32": 1, "bf16x6": 6, "fp16x3": 3}  # MFMA products per algorithmic product
+
+
+def phase_rates(wl, prec: str, phases: dict, rounds: int) -> dict:
+    """Algorithmic work of each phase, its rate and its fraction of the
+    roofline that bounds it.
+
+    kmeans : HBM bytes = weight pass (orbitals read once, w written) plus, per
+             round, w read and, once, the labels written.
+    factor : FLOPs of M = C C^H (real form) + Cholesky, triangular inverse and
+             W = Y^T Y of the real n1 x n1 matrix (n1^3 / 3 each).
+    zc     : 8 N_r N_mu (N_phi [+ N_psi]); split precisions issue 6x / 3x
+             as many 16-bit MFMA products, against the 16-bit peak.
+    solve  : 2 N_r n1^2 (FP64).
+    adjoint: Gram recompute 8 N_r N_mu N, orbital products Abar F and Abar^T X
+             16 N_r N_mu N, and the fused-loss FP64 products: H = G^T g G over
+             the lower half (N_r n1^2) and S = G M^-2 (2 N_r n1^2).
+    """
+    n_e = wl.n_phi + (0 if wl.aliased else wl.n_psi)
+    esize = 16
+    n1 = wl.n_mu if wl.aliased else 2 * wl.n_mu
+    out = {}
+    km_bytes = wl.n_r * n_e * esize + 8 * wl.n_r + rounds * 8 * wl.n_r + 4 * wl.n_r
+    ms = phases["kmeans"]
+    gbs = km_bytes / (ms * 1e-3) / 1e9
+    out["kmeans"] = {"ms": ms, "bound": "hbm", "bytes": km_bytes, "GB/s": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK, 4), "rounds": rounds,
+                     "brute_force_pairs": (rounds + 1) * wl.n_r * wl.n_mu}
+    work = {
+        "factor": (8.0 * wl.n_mu ** 2 * n_e + float(n1) ** 3, "fp64", 1),
+        "zc": (8.0 * wl.n_r * wl.n_mu * n_e, prec, ISSUED[prec]),
+        "solve": (2.0 * wl.n_r * n1 * n1, "fp64", 1),
+        "adjoint": (24.0 * wl.n_r * wl.n_mu * n_e + 3.0 * wl.n_r * n1 * n1, "fp64", 1),
+    }
+    for name, (flops, pk, issued) in work.items():
+        ms = phases[name]
+        tf = flops / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "bound": "mfma", "flops": flops, "TFLOP/s": round(tf, 2), "peak": MFMA_PEAK[pk],
+                     "frac": round(tf * issued / MFMA_PEAK[pk], 4)}
+        if issued != 1:
+            out[name]["issued_per_flop"] = issued
+    return out
+
+
 def cpu_baseline(d, idx, iters_run: int) -> dict:
     """The FP64 oracle on a bounded sample of the same workload, scaled to
     one full step (ms): weight at full size, two K-means rounds at full size
@@ -197,6 +242,7 @@ def main():
                                f"{'Phi=Psi' if wl.aliased else 'Phi!=Psi'}, K-means {wl.kmeans_iters} rounds, "
                                f"fit + fused-loss adjoint", "gram_prec": args.prec},
         "phases_ms": phases,
+        "phases": phase_rates(wl, args.prec, phases, info["kmeans"]["iters"]),
         "kmeans": {"rounds": info["kmeans"]["iters"], "converged": info["kmeans"]["converged"]},
         "roofline": {"bound": "mfma", "kernel": "FP64 GEMM Theta = (Z C^H)(C C^H)^-1",
                      "achieved": round(achieved, 2), "peak": PEAK["fp64"], "unit": "TFLOP/s",
@@ -213,6 +259,7 @@ def main():
             st2, ms2, _, ph2, _ = run(prec, args.steps, args.warmup)
             err = float(torch.linalg.norm(st2.theta.double() - theta64) / torch.linalg.norm(theta64))
             out["mixed"][prec] = {"ms_per_step": round(ms2, 3), "phases_ms": ph2,
+                                  "zc": phase_rates(wl, prec, ph2, out["kmeans"]["rounds"])["zc"],
                                   "theta_rel_err_vs_fp64_gpu": err, "speedup_vs_fp64": round(ms / ms2, 3)}
             del st2
             torch.cuda.empty_cache()
