@@ -186,14 +186,17 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    d = synth.make_workload(args.workload)
-    wl = d["wl"]
+    wl = synth.WORKLOADS[args.workload]
+    d = synth.make_workload(args.workload, log=log)
+    psi = torch.as_tensor(d["psi"]).cuda()
+    phi = psi if wl.aliased else psi[:, : wl.n_phi]
     log(f"[bench] workload {wl.name}: N_r={wl.n_r} N_e={wl.n_phi} N_mu={wl.n_mu} ({time.time() - t0:.1f}s)")
-    phi = torch.as_tensor(d["phi"]).cuda()
-    psi = phi if wl.aliased else torch.as_tensor(d["psi"]).cuda()
-    if not wl.aliased:
-        phi = psi[:, : wl.n_phi]
     g = torch.as_tensor(d["g"]).cuda()
+    if args.no_cpu_baseline:
+        d["phi"] = d["psi"] = None  # the host copy is only needed by the oracle
+    # grids whose Z C^H / Theta do not fit run the forward in streamed row blocks
+    block_rows = wl.rblock or None
+    rblock = wl.rblock or None
     torch.cuda.synchronize()
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 8
@@ -205,32 +208,37 @@ def main():
         del src, dst
 
     def run(prec, steps, warmup):
-        st = ISDFStep(phi, None if wl.aliased else psi, wl.n_mu, d["c0"], wl.kmeans_iters, g=g, prec=prec)
+        st = ISDFStep(phi, None if wl.aliased else psi, wl.n_mu, d["c0"], wl.kmeans_iters, g=g, prec=prec,
+                      rblock=rblock, block_rows=block_rows, keep_theta=block_rows is None)
         for _ in range(warmup):
             st.enqueue()
         info = st.check()
         ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-        solve = [(ev(), ev()) for _ in range(steps)]
-        phases = [[ev() for _ in range(6)] for _ in range(steps)]
+        nb = len(st.blocks)
+        blocks = [[(ev(), ev(), ev()) for _ in range(nb)] for _ in range(steps)]
+        phases = [[ev() for _ in range(5)] for _ in range(steps)]
         torch.cuda.synchronize()
         start, stop = ev(), ev()
         start.record()
         for k in range(steps):
-            st.enqueue(solve_events=solve[k], phase_events=phases[k])
+            st.enqueue(block_events=blocks[k], phase_events=phases[k])
         stop.record()
         torch.cuda.synchronize()
         info = st.check()
         total = start.elapsed_time(stop) / steps
-        solve_ms = sum(a.elapsed_time(b) for a, b in solve) / steps
-        names = ["kmeans", "factor", "zc", "solve", "adjoint"]
-        ph = {n: round(sum(p[i].elapsed_time(p[i + 1]) for p in phases) / steps, 3) for i, n in enumerate(names)}
-        return st, total, solve_ms, ph, info
+        zc_ms = sum(a.elapsed_time(b) for bl in blocks for a, b, _ in bl) / steps
+        solve_ms = sum(b.elapsed_time(c) for bl in blocks for _, b, c in bl) / steps
+        el = lambda i: sum(p[i].elapsed_time(p[i + 1]) for p in phases) / steps  # noqa: E731
+        ph = {"kmeans": round(el(0), 3), "factor": round(el(1), 3), "zc": round(zc_ms, 3),
+              "solve": round(solve_ms, 3), "adjoint": round(el(3), 3)}
+        return st, total, solve_ms / nb, ph, info
 
     log(f"[bench] {args.prec}: warmup {args.warmup}, timing {args.steps} steps")
     st, ms, solve_ms, phases, info = run(args.prec, args.steps, args.warmup)
     log(f"[bench] {args.prec}: {ms:.2f} ms/step, phases {phases}")
     n1 = wl.n_mu if wl.aliased else 2 * wl.n_mu
-    flops = 2.0 * wl.n_r * n1 * n1
+    nb = len(st.blocks)
+    flops = 2.0 * (wl.n_r / nb) * n1 * n1  # per launch (row blocks of equal size)
     achieved = flops / (solve_ms * 1e-3) / 1e12
     traffic = read_traffic(wl.name)
     out = {
@@ -240,7 +248,9 @@ def main():
         "dtype": "f64" if args.prec == "fp64" else args.prec, "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.n}^3 grid (N_r={wl.n_r}), N_e={wl.n_phi}, N_mu={wl.n_mu}, "
                                f"{'Phi=Psi' if wl.aliased else 'Phi!=Psi'}, K-means {wl.kmeans_iters} rounds, "
-                               f"fit + fused-loss adjoint", "gram_prec": args.prec},
+                               f"fit + fused-loss adjoint"
+                               + (f", Z C^H and Theta streamed in blocks of {block_rows} rows" if block_rows else ""),
+                   "gram_prec": args.prec},
         "phases_ms": phases,
         "phases": phase_rates(wl, args.prec, phases, info["kmeans"]["iters"]),
         "kmeans": {"rounds": info["kmeans"]["iters"], "converged": info["kmeans"]["converged"]},
@@ -250,7 +260,7 @@ def main():
                      "flops_per_launch": flops, "ms_per_launch": round(solve_ms, 3)},
     }
     if args.mixed:
-        theta64 = st.theta.clone()
+        theta64 = st.theta.clone()  # (the last block when streamed)
         del st
         torch.cuda.empty_cache()
         out["mixed"] = {}

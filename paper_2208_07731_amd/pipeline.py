@@ -4,6 +4,10 @@
     step.enqueue()          # K-means -> (C C^H)^-1 -> Z C^H -> Theta -> adjoint
     step.check()            # synchronises, raises on a device-side status
 
+With block_rows < N_r the forward runs Z C^H and Theta block by block
+(block_rows rows at a time); keep_theta=False then keeps only the current
+block of Theta (the streamed form for grids whose Theta does not fit).
+
 Nothing is allocated and nothing synchronises inside enqueue(): every
 output, workspace and info struct is created in the constructor, and the
 calls go straight to the C ABI on the current stream.  This is the form a
@@ -23,7 +27,8 @@ from .api import ISDFError, _orbital, _read_struct, _same
 class ISDFStep:
     def __init__(self, phi: torch.Tensor, psi: torch.Tensor | None, n_mu: int, c0, max_iter: int, *,
                  g: torch.Tensor | None = None, prec: str = "fp64", grid=None, h=(1.0, 1.0, 1.0),
-                 rblock: int | None = None, backward: bool = True, near_tie_rel: float = 1e-6):
+                 rblock: int | None = None, backward: bool = True, near_tie_rel: float = 1e-6,
+                 block_rows: int | None = None, keep_theta: bool = True):
         self.lib = L.load()
         psi = phi if psi is None else psi
         self.phi, self.psi = phi, psi
@@ -54,12 +59,16 @@ class ISDFStep:
         self.fit_info = torch.zeros(C.sizeof(L.FitInfo), dtype=u8, device=dev)
         self.fit_ws = torch.empty(self.lib.isdf_fit_workspace(C.byref(self.grid), n_mu, self.npf, self.nps,
                                                               int(self.aliased), self.prec, 1), dtype=u8, device=dev)
-        self.zc_ws = torch.empty(self.lib.isdf_zc_workspace(n_mu, self.npf, self.nps, int(self.aliased), self.prec, n_r),
-                                 dtype=u8, device=dev)
-        self.G = torch.empty(n_r, self.n1, dtype=f64, device=dev)
+        self.block_rows = n_r if block_rows is None else min(int(block_rows), n_r)
+        self.blocks = [(r, min(self.block_rows, n_r - r)) for r in range(0, n_r, self.block_rows)]
+        self.keep_theta = keep_theta or len(self.blocks) == 1
+        self.zc_ws = torch.empty(self.lib.isdf_zc_workspace(n_mu, self.npf, self.nps, int(self.aliased), self.prec,
+                                                            self.block_rows), dtype=u8, device=dev)
+        self.G = torch.empty(self.block_rows, self.n1, dtype=f64, device=dev)
         real_t = f64 if self.dt == L.C128 else torch.float32
         cplx_t = torch.complex128 if self.dt == L.C128 else torch.complex64
-        self.theta = torch.empty(n_r, n_mu, dtype=real_t if self.aliased else cplx_t, device=dev)
+        self.theta = torch.empty(n_r if self.keep_theta else self.block_rows, n_mu,
+                                 dtype=real_t if self.aliased else cplx_t, device=dev)
         if backward:
             if g is None:
                 raise ValueError("the adjoint needs the loss field g")
@@ -76,14 +85,15 @@ class ISDFStep:
         if code != L.OK:
             raise ISDFError(code, where)
 
-    def enqueue(self, solve_events=None, phase_events=None):
-        """Enqueue the step on the current stream.  solve_events=(start, stop)
-        brackets the launch that applies (C C^H)^-1 to Z C^H; phase_events (6
-        events) are recorded before K-means and after K-means, the
-        factorisation, Z C^H, Theta and the adjoint."""
+    def enqueue(self, block_events=None, phase_events=None):
+        """Enqueue the step on the current stream.  block_events (one triple
+        of events per row block) bracket each block's Z C^H and Theta
+        launches; phase_events (5 events) are recorded before K-means and
+        after K-means, the factorisation, the last Theta block and the
+        adjoint."""
         lib, s = self.lib, torch.cuda.current_stream().cuda_stream
         gp = C.byref(self.grid)
-        ph = phase_events or [None] * 6
+        ph = phase_events or [None] * 5
 
         def mark(i):
             if ph[i] is not None:
@@ -101,18 +111,22 @@ class ISDFStep:
                                 None, self.n_mu, 1, self.fit_info.data_ptr(), self.fit_ws.data_ptr(),
                                 self.fit_ws.numel(), s), "isdf_fit")
         mark(2)
-        self._call(lib.isdf_zc(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
-                               self.idx.data_ptr(), self.n_mu, self.prec, 0, self.n_r, self.G.data_ptr(), self.n1,
-                               self.zc_ws.data_ptr(), self.zc_ws.numel(), s), "isdf_zc")
+        esz = self.theta.element_size()
+        for b, (r0, nrows) in enumerate(self.blocks):
+            be = block_events[b] if block_events else None
+            if be:
+                be[0].record()
+            self._call(lib.isdf_zc(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
+                                   self.idx.data_ptr(), self.n_mu, self.prec, r0, nrows, self.G.data_ptr(), self.n1,
+                                   self.zc_ws.data_ptr(), self.zc_ws.numel(), s), "isdf_zc")
+            if be:
+                be[1].record()
+            th = self.theta.data_ptr() + (r0 * self.n_mu * esz if self.keep_theta else 0)
+            self._call(lib.isdf_apply_minv(self.n_mu, int(self.aliased), self.minv.data_ptr(), self.G.data_ptr(),
+                                           self.n1, nrows, self.dt, th, self.n_mu, s), "isdf_apply_minv")
+            if be:
+                be[2].record()
         mark(3)
-        if solve_events:
-            solve_events[0].record()
-        self._call(lib.isdf_apply_minv(self.n_mu, int(self.aliased), self.minv.data_ptr(), self.G.data_ptr(),
-                                       self.n1, self.n_r, self.dt, self.theta.data_ptr(), self.n_mu, s),
-                   "isdf_apply_minv")
-        if solve_events:
-            solve_events[1].record()
-        mark(4)
         if self.backward:
             self._call(lib.isdf_fit_backward(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
                                              self.idx.data_ptr(), self.n_mu, self.prec, self.minv.data_ptr(), None,
@@ -120,7 +134,7 @@ class ISDFStep:
                                              self.dpsi.data_ptr(), self.nps, self.loss.data_ptr(), self.rblock,
                                              self.bwd_info.data_ptr(), self.bwd_ws.data_ptr(), self.bwd_ws.numel(),
                                              s), "isdf_fit_backward")
-        mark(5)
+        mark(4)
 
     def check(self) -> dict:
         """Synchronise and return the device-side infos; raise on errors."""

@@ -8,6 +8,7 @@ from .orbitals import (  # noqa: F401
     WORKLOADS,
     Workload,
     make_workload,
+    make_orbitals_large,
     make_orbitals,
     init_centroids,
     loss_field,

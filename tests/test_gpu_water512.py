@@ -1,0 +1,129 @@
+"""Full-size parity of the 512-water workload (128^3 grid, N_r = 2097152,
+N_e = 1024, N_mu = 8192; 34 GB of complex128 orbitals) on outputs the oracle
+can compute one by one:
+
+* the SSM weight and the first classification at sampled grid points;
+* rows of Theta in two r-blocks of 65536 rows (FP64 and BF16x6), plus the
+  interpolation property at the interpolation points inside those blocks;
+* the fused-loss gradient at sampled grid points that are not interpolation
+  points.  Theta, S = Thetabar M^-1, Abar and dPhi rows are row-local given
+  Phi_mu, so the oracle evaluates them on the sub-problem made of the
+  interpolation rows and the sampled rows.
+
+Generating the inputs takes one to two minutes of host time and about 40 GB
+of host memory, so the module runs only with ISDF_WATER512=1.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("ISDF_WATER512") != "1",
+                                 reason="512-water inputs take minutes of host time; set ISDF_WATER512=1")]
+
+isdf = pytest.importorskip("paper_2208_07731_amd")
+
+EPS = np.finfo(np.float64).eps
+BLOCK = 65536
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def c5():
+    print("[water512] generating orbitals on the host", flush=True)
+    d = synth.make_workload("water512", log=lambda s: print(s, flush=True))
+    wl = d["wl"]
+    host = d["phi"]
+    print("[water512] copying to the GPU", flush=True)
+    d["phi"] = torch.as_tensor(host).cuda()
+    c0 = np.asarray(d["c0"], dtype=np.int64)  # distinct grid points
+    idx = ((c0[:, 0] * wl.n + c0[:, 1]) * wl.n + c0[:, 2]).astype(np.int32)
+    rng = np.random.default_rng(5005)
+    blocks = [0, 17 * BLOCK]
+    others = np.setdiff1d(np.concatenate([np.arange(b, b + BLOCK) for b in blocks]), idx)
+    sample = np.sort(rng.choice(others, 256, replace=False))
+    sub_rows = np.concatenate([idx, sample])
+    phi_sub = np.ascontiguousarray(host[sub_rows])
+    wpts = np.random.default_rng(5006).choice(wl.n_r, 8192, replace=False)
+    w_ref = oracle.weight(np.ascontiguousarray(host[wpts]), None)
+    del host
+    loc = np.arange(wl.n_mu)
+    print("[water512] oracle fit on the sub-problem", flush=True)
+    ref = oracle.fit(phi_sub, phi_sub, loc)
+    # 1-norm condition estimate of C C^H from its Cholesky factor (LAPACK pocon)
+    M = ref["M"].real
+    rcond, _ = sla.lapack.dpocon(np.asfortranarray(ref["L"].real.T), np.linalg.norm(M, 1), uplo="U")
+    kappa = 1.0 / rcond
+    print(f"[water512] kappa_1(C C^H) ~ {kappa:.3e}", flush=True)
+    return dict(d=d, wl=wl, idx=idx, blocks=blocks, sample=sample, phi_sub=phi_sub, ref=ref, kappa=kappa,
+                wpts=wpts, w_ref=w_ref)
+
+
+def test_water512_weight_and_first_classification(c5):
+    d, wl = c5["d"], c5["wl"]
+    r = isdf.kmeans(d["phi"], None, wl.n_mu, d["c0"], 0, grid=wl.n)
+    pts = c5["wpts"]
+    pt = torch.as_tensor(pts, device="cuda")
+    w_ref = c5["w_ref"]
+    assert np.max(np.abs(r.w[pt].cpu().numpy() - w_ref) / w_ref) <= 1e-13
+    grid = oracle.grid_points(wl.n)[pts]
+    lab, d1, d2 = oracle.assign(grid, np.asarray(d["c0"], dtype=np.float64), oracle.metric_scale())
+    ok = ~(np.isfinite(d2) & (d2 - d1 <= 1e-6 * d2))
+    got = r.labels[pt].cpu().numpy()
+    assert np.array_equal(got[ok], lab[ok])
+    # every interpolation point is a member of its own cluster
+    idx = r.idx.cpu().numpy()
+    live = idx >= 0
+    assert np.array_equal(r.labels.cpu().numpy()[idx[live]], np.nonzero(live)[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+def test_water512_theta_rows(c5, prec):
+    d, wl = c5["d"], c5["wl"]
+    idx_t = torch.as_tensor(c5["idx"], device="cuda")
+    _, minv, _ = isdf.fit(d["phi"], None, idx_t, nrows=0, prec=prec)
+    ref = c5["ref"]["theta"].real[wl.n_mu:]
+    got = np.empty_like(ref)
+    for b in c5["blocks"]:
+        th, _, _ = isdf.fit(d["phi"], None, idx_t, minv=minv, factor=False, row0=b, nrows=BLOCK, rblock=BLOCK,
+                            prec=prec)
+        sel = (c5["sample"] >= b) & (c5["sample"] < b + BLOCK)
+        got[sel] = th[torch.as_tensor(c5["sample"][sel] - b, device="cuda")].cpu().numpy()
+        inside = np.nonzero((c5["idx"] >= b) & (c5["idx"] < b + BLOCK))[0]
+        if prec == "fp64" and inside.size:
+            rows = th[torch.as_tensor(c5["idx"][inside] - b, device="cuda")].cpu().numpy()
+            eye = np.zeros_like(rows)
+            eye[np.arange(inside.size), inside] = 1.0
+            assert np.max(np.abs(rows - eye)) <= 10 * c5["kappa"] * EPS
+        del th
+    err = rel(got, ref)
+    print(f"[water512] {prec} theta rel err {err:.3e}")
+    assert err <= (max(1e-12, 4 * c5["kappa"] * EPS) if prec == "fp64" else 1e-6)
+
+
+def test_water512_fused_loss_gradient_rows(c5):
+    d, wl = c5["d"], c5["wl"]
+    idx_t = torch.as_tensor(c5["idx"], device="cuda")
+    g = d["g"]
+    _, minv, _ = isdf.fit(d["phi"], None, idx_t, nrows=0)
+    print("[water512] adjoint on the GPU", flush=True)
+    dphi, dpsi, loss, info = isdf.fit_backward(d["phi"], None, idx_t, minv, g=torch.as_tensor(g, device="cuda"),
+                                               rblock=BLOCK)
+    got = dphi[torch.as_tensor(c5["sample"], device="cuda")].cpu().numpy()
+    del dphi, dpsi
+    sub_rows = np.concatenate([c5["idx"], c5["sample"]])
+    print("[water512] oracle adjoint on the sub-problem", flush=True)
+    ref = oracle.fit_backward(c5["phi_sub"], c5["phi_sub"], np.arange(wl.n_mu), g=g[sub_rows])
+    err = rel(got, ref["dphi"][wl.n_mu:])
+    print(f"[water512] dphi rows rel err {err:.3e}")
+    assert err <= max(1e-11, 1e2 * c5["kappa"] * EPS)
+    assert info["status"] == 0 and np.isfinite(loss.item()) and loss.item() > 0
