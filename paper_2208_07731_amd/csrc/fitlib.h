@@ -222,7 +222,7 @@ __global__ void fit_finish(const FitState* st, isdf_fit_info* info, double* loss
 
 // ------------------------------------------------------------ launches
 template <class T, int BM, int BN, int BK, int WM, int WN, class TA, int LA, class TB, int LB, int NOPS,
-          class Epi>
+          int FOLD = 0, class Epi>
 static bool launch_gemm(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0, Operand<TA> A1,
                         Operand<TB> B1, int64_t K1, const Epi& epi, int lower_only, const int* abort,
                         hipStream_t st, int splits = 1, int batch = 1, int64_t sa = 0, int64_t sb = 0) {
@@ -239,7 +239,7 @@ static bool launch_gemm(int M, int N, int64_t K, Operand<TA> A0, Operand<TB> B0,
   sh.sb = sb;
   const int64_t tiles = gemm_tiles((int)ceil_div(M, BM), (int)ceil_div(N, BN), sh.lower_only);
   dim3 grid((unsigned)(tiles * splits), (unsigned)batch, 1);
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, TA, LA, TB, LB, NOPS, Epi>), grid,
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, BK, WM, WN, TA, LA, TB, LB, NOPS, Epi, FOLD>), grid,
                      dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, epi);
   return launch_ok();
 }
@@ -372,6 +372,9 @@ struct Prec<ISDF_P_FP16X3> {
   static constexpr int SPLIT = SPLIT_FP16X3;
 };
 
+// Slices between FP64 folds of the leading accumulator.
+constexpr int SPLIT_FLUSH = 2;
+
 template <int MODE, int BM, int BN, int WM, int WN, int NOPS, class Epi>
 static bool launch_split(int M, int N, int64_t K, PlaneOp<typename SplitT<MODE>::P> A0,
                          PlaneOp<typename SplitT<MODE>::P> B0, PlaneOp<typename SplitT<MODE>::P> A1,
@@ -386,7 +389,7 @@ static bool launch_split(int M, int N, int64_t K, PlaneOp<typename SplitT<MODE>:
   sh.splits = 1;
   sh.abort = abort;
   const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
-  hipLaunchKernelGGL((gemm_split_kernel<MODE, BM, BN, WM, WN, NOPS, Epi>), dim3((unsigned)tiles),
+  hipLaunchKernelGGL((gemm_split_kernel<MODE, BM, BN, WM, WN, NOPS, SPLIT_FLUSH, Epi>), dim3((unsigned)tiles),
                      dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, scales, epi);
   return launch_ok();
 }
@@ -492,11 +495,13 @@ static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_
     PlaneOp<P> pb1{(const P*)sw->e_b, sw->ldp_b, (int64_t)sw->e_rows * sw->ldp_b, nullptr};
     return launch_split<SPLIT, 64, 64, 2, 2, 2>(rows, N, sw->ldp_a, pa0, pb0, pa1, pb1, sw->ldp_b, sc, epi, abort, s);
   } else {
+    // FP32: accumulators folded into FP64 every 2 steps (32-deep)
+    constexpr int FOLD = sizeof(T) == 4 ? 2 : 0;
     if (aliased)
-      return launch_gemm<T, 128, 128, 16, 2, 2, TS, KC, T, KC, 1>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0, 0,
-                                                                   epi, 0, abort, s);
-    return launch_gemm<T, 128, 64, 16, 2, 2, TS, KC, T, KC, 2>(rows, N, 2 * (int64_t)n_phi, a0, b0, a1, b1,
-                                                                2 * (int64_t)n_psi, epi, 0, abort, s);
+      return launch_gemm<T, 128, 128, 16, 2, 2, TS, KC, T, KC, 1, FOLD>(rows, N, 2 * (int64_t)n_phi, a0, b0, a0, b0,
+                                                                         0, epi, 0, abort, s);
+    return launch_gemm<T, 128, 64, 16, 2, 2, TS, KC, T, KC, 2, FOLD>(rows, N, 2 * (int64_t)n_phi, a0, b0, a1, b1,
+                                                                      2 * (int64_t)n_psi, epi, 0, abort, s);
   }
 }
 

@@ -226,14 +226,35 @@ __device__ __forceinline__ void read4(const T* s, int x, int c, int lane, T (&o)
   }
 }
 
+// FP64 accumulator set of a tile (the target of folded FP32 accumulators).
+template <class Cfg>
+struct FoldAcc {
+  d4v v[Cfg::MI][Cfg::NI];
+};
+
+template <class Cfg, class A>
+__device__ __forceinline__ void fold_into(A (&acc)[Cfg::MI][Cfg::NI], FoldAcc<Cfg>& f) {
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::NI; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) f.v[i][j][r] += (double)acc[i][j][r];
+      acc[i][j] = A{0, 0, 0, 0};
+    }
+}
+
 // Runs the K loop of one operand pair into acc.  LDS is double buffered:
 // the slice for step i+1 is loaded from global memory while step i feeds the
 // MFMAs, stored into the other buffer, and one barrier per step separates
-// the two.
-template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK>
+// the two.  FOLD > 0 (FP32 only): acc is added into the FP64 set `fold`
+// and cleared every FOLD steps and at the end, so FP32 rounding of the
+// running sums does not grow with K.
+template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0>
 __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
                                          int N, int64_t kbeg, int64_t kend, T* smem,
-                                         typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI]) {
+                                         typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI],
+                                         FoldAcc<Cfg>* fold = nullptr) {
   typedef Lds<T, LA, BM, BK> LA_;
   typedef Lds<T, LB, BN, BK> LB_;
   constexpr int STAGE = LA_::SIZE + LB_::SIZE;
@@ -256,6 +277,7 @@ __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>
   sb.store(smem + LA_::SIZE, tid);
   __syncthreads();
   int cur = 0;
+  int step = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) {
@@ -278,6 +300,12 @@ __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>
 #pragma unroll
           for (int j = 0; j < Cfg::NI; ++j) MfmaT<T>::mma(a[i][s], b[j][s], acc[i][j]);
     }
+    if constexpr (FOLD > 0) {
+      if (++step == FOLD) {
+        step = 0;
+        fold_into<Cfg>(acc, *fold);
+      }
+    }
     if (more) {
       T* nxt = smem + (cur ^ 1) * STAGE;
       sa.store(nxt, tid);
@@ -286,6 +314,7 @@ __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>
     __syncthreads();
     cur ^= 1;
   }
+  if constexpr (FOLD > 0) fold_into<Cfg>(acc, *fold);
 }
 
 // Tile coordinates handed to epilogues.
@@ -299,10 +328,11 @@ struct TileAt {
 // Generic kernel: NOPS = 1 (one operand pair) or 2 (two pairs into two
 // accumulator sets, same tile, e.g. Phi and Psi Gram blocks).
 template <class T, int BM, int BN, int BK, int WM, int WN, class TA, int LA, class TB, int LB, int NOPS,
-          class Epi>
+          class Epi, int FOLD = 0>
 __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh, Operand<TA> A0, Operand<TB> B0,
                                                                  Operand<TA> A1, Operand<TB> B1, int64_t K1,
                                                                  Epi epi) {
+  static_assert(FOLD == 0 || sizeof(T) == 4, "folding is for FP32 accumulators");
   typedef TileCfg<T, BM, BN, BK, WM, WN> Cfg;
   if (sh.abort && *sh.abort) return;
   constexpr int STAGE = Lds<T, LA, BM, BK>::SIZE + Lds<T, LB, BN, BK>::SIZE;
@@ -341,28 +371,49 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh
   const int64_t kbeg = (int64_t)z * sh.kchunk;
   const int64_t kend = kbeg + sh.kchunk < sh.K ? kbeg + sh.kchunk : sh.K;
 
-  typename MfmaT<T>::acc_t acc0[Cfg::MI][Cfg::NI];
+  typedef typename MfmaT<T>::acc_t acc_t;
+  acc_t acc0[Cfg::MI][Cfg::NI];
 #pragma unroll
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
-    for (int j = 0; j < Cfg::NI; ++j) acc0[i][j] = typename MfmaT<T>::acc_t{0, 0, 0, 0};
-  mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK>(A0, B0, m0, n0, sh.M, sh.N, kbeg, kend, smem, acc0);
+    for (int j = 0; j < Cfg::NI; ++j) acc0[i][j] = acc_t{0, 0, 0, 0};
+  FoldAcc<Cfg> f0;
+  if constexpr (FOLD > 0) {
+#pragma unroll
+    for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::NI; ++j) f0.v[i][j] = d4v{0, 0, 0, 0};
+  }
+  mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD>(A0, B0, m0, n0, sh.M, sh.N, kbeg, kend, smem, acc0, &f0);
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int wm = wv / (BN / Cfg::WTN), wn = wv % (BN / Cfg::WTN);
   TileAt at{m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, z, batch};
   if constexpr (NOPS == 2) {
-    typename MfmaT<T>::acc_t acc1[Cfg::MI][Cfg::NI];
+    acc_t acc1[Cfg::MI][Cfg::NI];
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j) acc1[i][j] = typename MfmaT<T>::acc_t{0, 0, 0, 0};
+      for (int j = 0; j < Cfg::NI; ++j) acc1[i][j] = acc_t{0, 0, 0, 0};
+    FoldAcc<Cfg> f1;
+    if constexpr (FOLD > 0) {
+#pragma unroll
+      for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::NI; ++j) f1.v[i][j] = d4v{0, 0, 0, 0};
+    }
     __syncthreads();
-    mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK>(A1, B1, m0, n0, sh.M, sh.N, 0, K1, smem, acc1);
-    epi.template apply2<Cfg>(acc0, acc1, at);
+    mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD>(A1, B1, m0, n0, sh.M, sh.N, 0, K1, smem, acc1, &f1);
+    if constexpr (FOLD > 0)
+      epi.template apply2<Cfg>(f0.v, f1.v, at);
+    else
+      epi.template apply2<Cfg>(acc0, acc1, at);
   } else {
-    epi.template apply<Cfg>(acc0, at);
+    if constexpr (FOLD > 0)
+      epi.template apply<Cfg>(f0.v, at);
+    else
+      epi.template apply<Cfg>(acc0, at);
   }
 }
 

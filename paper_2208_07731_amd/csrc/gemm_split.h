@@ -15,8 +15,9 @@
 //
 // The leading product and the correction products accumulate in separate
 // FP32 accumulators (the corrections are 2^-8 or 2^-11 smaller, so their
-// rounding stays negligible and the leading sum sees one rounding per
-// 32-deep MFMA), and the epilogue receives their sum in FP64.
+// rounding stays negligible); the leading accumulator is folded into FP64
+// every FLUSH 32-deep slices, so FP32 rounding does not grow with K, and the
+// epilogue receives the FP64 sum.
 //
 // MFMA: v_mfma_f32_16x16x32_bf16 / _f16.  Operand lane layout (checked on
 // the hardware): lane l holds row/column l % 16 and k = 8 (l / 16) + e,
@@ -135,13 +136,29 @@ struct PlaneStager {
   }
 };
 
-// K loop of one operand pair into the leading (acc0) and correction (acc1)
-// accumulators.  Single LDS buffer, the next slice prefetched in registers.
-template <int MODE, class Cfg, int BM, int BN>
+// Leading-product accumulator folded into FP64 every FLUSH 32-deep slices:
+// FP32 then sums at most 32 FLUSH products per output before a rounding that
+// grows with K can build up.
+template <class Cfg>
+__device__ __forceinline__ void flush_acc(f4v (&acc)[Cfg::MI][Cfg::NI], d4v (&accd)[Cfg::MI][Cfg::NI]) {
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::NI; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accd[i][j][r] += (double)acc[i][j][r];
+      acc[i][j] = f4v{0, 0, 0, 0};
+    }
+}
+
+// K loop of one operand pair into the leading (acc0, folded into accd every
+// FLUSH slices) and correction (acc1) accumulators.  Single LDS buffer, the
+// next slice prefetched in registers.
+template <int MODE, class Cfg, int BM, int BN, int FLUSH>
 __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::P>& A,
                                            const PlaneOp<typename SplitT<MODE>::P>& B, int m0, int n0, int M, int N,
                                            int64_t K, typename SplitT<MODE>::P* smem, f4v (&acc0)[Cfg::MI][Cfg::NI],
-                                           f4v (&acc1)[Cfg::MI][Cfg::NI]) {
+                                           f4v (&acc1)[Cfg::MI][Cfg::NI], d4v (&accd)[Cfg::MI][Cfg::NI]) {
   typedef SplitT<MODE> S;
   typedef typename S::P P;
   typedef typename S::V V;
@@ -161,6 +178,7 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
   sb.store(Bs, LDK, tid);
   __syncthreads();
   const int q8 = 8 * (lane >> 4);
+  int step = 0;
   for (int64_t k0 = 0; k0 < K; k0 += Cfg::BK) {
     const bool more = k0 + Cfg::BK < K;
     if (more) {
@@ -187,6 +205,10 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j) S::mma(a[0][i], b[0][j], acc0[i][j]);
+    if (++step == FLUSH) {
+      step = 0;
+      flush_acc<Cfg>(acc0, accd);
+    }
     __syncthreads();
     if (more) {
       sa.store(As, LDK, tid);
@@ -194,6 +216,7 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
       __syncthreads();
     }
   }
+  flush_acc<Cfg>(acc0, accd);
 }
 
 // Split of rows of an r-major complex matrix (or a real matrix read as
@@ -241,7 +264,7 @@ __device__ __forceinline__ double pow2_scale_for(double amax) {
 // NOPS = 1 or 2 operand pairs (two pairs: two accumulator sets, e.g. the
 // Gram blocks of Phi and Psi for the same tile).  scales: null (BF16X6) or
 // device [s_A0, s_B0, s_A1, s_B1] the planes were scaled by (FP16X3).
-template <int MODE, int BM, int BN, int WM, int WN, int NOPS, class Epi>
+template <int MODE, int BM, int BN, int WM, int WN, int NOPS, int FLUSH, class Epi>
 __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
     GemmShape sh, PlaneOp<typename SplitT<MODE>::P> A0, PlaneOp<typename SplitT<MODE>::P> B0,
     PlaneOp<typename SplitT<MODE>::P> A1, PlaneOp<typename SplitT<MODE>::P> B1, int64_t K1, const double* scales,
@@ -268,28 +291,34 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
 #pragma unroll
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
-    for (int j = 0; j < Cfg::NI; ++j) c0[i][j] = c1[i][j] = f4v{0, 0, 0, 0};
-  split_loop<MODE, Cfg, BM, BN>(A0, B0, m0, n0, sh.M, sh.N, sh.K, smem, c0, c1);
+    for (int j = 0; j < Cfg::NI; ++j) {
+      c0[i][j] = c1[i][j] = f4v{0, 0, 0, 0};
+      r0[i][j] = d4v{0, 0, 0, 0};
+    }
+  split_loop<MODE, Cfg, BM, BN, FLUSH>(A0, B0, m0, n0, sh.M, sh.N, sh.K, smem, c0, c1, r0);
 #pragma unroll
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
     for (int j = 0; j < Cfg::NI; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) r0[i][j][r] = ((double)c0[i][j][r] + (double)c1[i][j][r]) * u0;
+      for (int r = 0; r < 4; ++r) r0[i][j][r] = (r0[i][j][r] + (double)c1[i][j][r]) * u0;
   if constexpr (NOPS == 2) {
+    d4v r1[Cfg::MI][Cfg::NI];
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j) c0[i][j] = c1[i][j] = f4v{0, 0, 0, 0};
+      for (int j = 0; j < Cfg::NI; ++j) {
+        c0[i][j] = c1[i][j] = f4v{0, 0, 0, 0};
+        r1[i][j] = d4v{0, 0, 0, 0};
+      }
     __syncthreads();
-    split_loop<MODE, Cfg, BM, BN>(A1, B1, m0, n0, sh.M, sh.N, K1, smem, c0, c1);
-    d4v r1[Cfg::MI][Cfg::NI];
+    split_loop<MODE, Cfg, BM, BN, FLUSH>(A1, B1, m0, n0, sh.M, sh.N, K1, smem, c0, c1, r1);
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) r1[i][j][r] = ((double)c0[i][j][r] + (double)c1[i][j][r]) * u1;
+        for (int r = 0; r < 4; ++r) r1[i][j][r] = (r1[i][j][r] + (double)c1[i][j][r]) * u1;
     epi.template apply2<Cfg>(r0, r1, at);
   } else {
     epi.template apply<Cfg>(r0, at);

@@ -133,8 +133,7 @@ def test_fit_sio2_mixed_precision_sampled_rows(sio2_case, prec, dtype):
     precision and the factorisation and solve in FP64.  The error is measured
     against (i) the oracle on the c128 data and, for c64 storage, (ii) the
     oracle on the c64 data upcast (arithmetic error alone).  The target is
-    1e-6 relative for the split precisions; FP32 accumulates 2 N_e-deep sums
-    in single precision and is held to 1e-5."""
+    1e-6 relative for every precision."""
     c = sio2_case
     d, wl = c["d"], c["wl"]
     psi = d["psi"] if dtype == "c128" else d["psi"].astype(np.complex64)
@@ -151,7 +150,7 @@ def test_fit_sio2_mixed_precision_sampled_rows(sio2_case, prec, dtype):
         ref2 = oracle.fit(up[:, : wl.n_phi], up, c["idx"], rows=c["rows"])
         err = rel(got, ref2["theta"])
         print(f"sio2 {prec} c64 theta rel err {err:.3e} vs upcast oracle, {err_i:.3e} vs c128 oracle")
-    assert err <= (1e-5 if prec == "fp32" else 1e-6)
+    assert err <= 1e-6
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

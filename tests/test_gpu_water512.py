@@ -44,7 +44,7 @@ def c5():
     wl = d["wl"]
     host = d["phi"]
     print("[water512] copying to the GPU", flush=True)
-    d["phi"] = torch.as_tensor(host).cuda()
+    d["phi"] = d["psi"] = torch.as_tensor(host).cuda()
     c0 = np.asarray(d["c0"], dtype=np.int64)  # distinct grid points
     idx = ((c0[:, 0] * wl.n + c0[:, 1]) * wl.n + c0[:, 2]).astype(np.int32)
     rng = np.random.default_rng(5005)
