@@ -23,7 +23,7 @@
 namespace isdf {
 namespace {
 
-constexpr int MAX_SPLITS = 16;
+constexpr int MAX_SPLITS = 32;
 
 // Abar / Bbar from S and the block's Gram blocks, in place.
 //  aliased: S real [R][n_mu]; A complex -> Abar = S A (over A)
@@ -242,15 +242,50 @@ static unsigned blocks_for(int64_t n) {
   return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
 }
 
-// Split-K factor: enough workgroups to fill the chip, slices of at least 512
-// rows, a multiple of 8 when possible (one K slice per XCD at a time).
-static int splits_for(int64_t tiles, int64_t K) {
-  int s = (int)(2048 / (tiles > 0 ? tiles : 1));
-  if (s > MAX_SPLITS) s = MAX_SPLITS;
-  const int64_t kmax = ceil_div(K, 512);
-  if (s > kmax) s = (int)kmax;
-  if (s >= 8) s -= s % 8;
-  return s < 1 ? 1 : s;
+// Workgroup slots of the current device: two 128 x 128 FP64 tiles per CU.
+static int device_slots() {
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cu <= 0)
+    cu = 256;
+  return 2 * cu;
+}
+
+// Split-K factor of a 128 x 128-tiled product with `tiles` output tiles of
+// mn elements in total and K-deep sums: 1 or a multiple of 8 (one K slice per
+// XCD at a time), slices of at least 512 rows, chosen to minimise
+// the modelled time ceil(tiles s / slots) (K / s) t_row + s mn 16 B / bw,
+// i.e. whole waves of workgroups against the partial sums' write and read.
+static int splits_for(int64_t tiles, int64_t K, int64_t mn, int slots) {
+  const double t_row = 2.0 * 128 * 128 / (60e12 / slots);  // s per k-row and tile
+  const double bw = 4e12;                                   // B/s for the partials
+  int best = 1;
+  double best_t = 0.0;
+  for (int s = 1; s <= MAX_SPLITS; s = s < 8 ? 8 : s + 8) {
+    if (s > 1 && ceil_div(K, s) < 512) break;
+    const double waves = (double)ceil_div(tiles * s, (int64_t)slots);
+    const double t = waves * ((double)K / s) * t_row + (s > 1 ? s * (double)mn * 16.0 / bw : 0.0);
+    if (s == 1 || t < best_t * (1.0 - 1e-9)) {
+      best = s;
+      best_t = t;
+    }
+  }
+  return best;
+}
+
+// Split factors the adjoint uses for blocks of `rows` rows.
+struct BwdSplits {
+  int h;  // Theta^T S (general) or H = G^T g G (fused, lower tiles)
+  int q;  // Abar^T X per orbital set
+};
+
+static BwdSplits bwd_splits(int64_t rows, int64_t n1, int n_mu, int n, bool fused, int slots) {
+  const int64_t t1 = ceil_div(n1, 128);
+  BwdSplits b;
+  b.h = splits_for(fused ? gemm_tiles((int)t1, (int)t1, 1) : t1 * t1, rows, n1 * n1, slots);
+  b.q = splits_for(ceil_div(2 * (int64_t)n_mu, 128) * ceil_div(2 * (int64_t)n, 128), rows,
+                   2 * (int64_t)n_mu * 2 * n, slots);
+  return b;
 }
 
 // Planes of the adjoint's orbital products dX = Abar F (split precisions):
@@ -285,12 +320,24 @@ struct BwdPlan {
   double* sc;    // [12] operand scales: Gram (4), dPhi (2), dPsi (2), padding
   SplitWork sw;  // orbital-row and Gram right-hand-side planes (split precisions)
   AdjPlanes ap;  // Abar / Bbar and F planes (split precisions)
+  int slots;     // workgroup slots the split factors were chosen for
   size_t bytes;
 };
 
-static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bool aliased, isdf_prec prec,
-                        int64_t rblock) {
+static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, int n_psi, bool aliased,
+                        isdf_prec prec, int64_t rblock, int slots) {
   const size_t tsize = tsize_of(prec);
+  // largest split factors over the block sizes that occur (both losses)
+  int sh = 1, sq = 1;
+  for (int64_t rows : {rblock, nr - (ceil_div(nr, rblock) - 1) * rblock})
+    for (bool fused : {false, true}) {
+      const int64_t n1b = aliased ? n_mu : 2 * (int64_t)n_mu;
+      const BwdSplits b1 = bwd_splits(rows, n1b, n_mu, n_phi, fused, slots);
+      const BwdSplits b2 = bwd_splits(rows, n1b, n_mu, n_psi, fused, slots);
+      sh = b1.h > sh ? b1.h : sh;
+      sq = b1.q > sq ? b1.q : sq;
+      sq = b2.q > sq ? b2.q : sq;
+    }
   Carver c(ws, cap);
   BwdPlan P{};
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
@@ -313,10 +360,11 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bo
   if (!aliased) P.B = c.take<double>((size_t)rblock * 2 * n_mu);
   P.P = c.take<double>((size_t)n1 * n1);
   P.W2 = c.take<double>((size_t)n1 * n1);
-  P.Ppart = c.take<double>((size_t)MAX_SPLITS * n1 * n1);
+  P.Ppart = c.take<double>((size_t)sh * n1 * n1);
+  P.slots = slots;
   P.Qphi = c.take<double>((size_t)2 * n_mu * 2 * n_phi);
   if (!aliased) P.Qpsi = c.take<double>((size_t)2 * n_mu * 2 * n_psi);
-  P.Qpart = c.take<double>((size_t)MAX_SPLITS * 2 * n_mu * 2 * nmax);
+  P.Qpart = c.take<double>((size_t)sq * 2 * n_mu * 2 * nmax);
   P.Amu = c.take<double>((size_t)n_mu * 2 * n_mu);
   if (!aliased) P.Bmu = c.take<double>((size_t)n_mu * 2 * n_mu);
   P.dA = c.take<double>((size_t)n_mu * 2 * n_mu);
@@ -360,12 +408,11 @@ static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec
 template <int PREC, class TS>
 static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const void* fplanes,
                           const TS* X, int64_t ld_x, int n, TS* dX, int64_t ld_dx, int64_t r, int rows, double* Q,
-                          double* Qpart, const double* scales, const AdjPlanes& ap, const int* ab, hipStream_t s) {
+                          double* Qpart, const double* scales, const AdjPlanes& ap, int sp, const int* ab,
+                          hipStream_t s) {
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s))
     return false;
-  const int64_t tiles = ceil_div(two_mu, 128) * ceil_div(2 * n, 128);
-  const int sp = splits_for(tiles, rows);
   const int64_t qn = two_mu * 2 * n;
   if (!tgemm<typename Prec<PREC>::Q, XC, XC>((int)two_mu, 2 * n, rows, Abar, two_mu, X + 2 * r * ld_x, 2 * ld_x,
                                              Qpart, 2 * (int64_t)n, 1.0, 0.0, ab, s, sp, qn))
@@ -439,10 +486,11 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
     if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr, r,
                         rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, &P.sw, P.A, aliased ? nullptr : P.B))
       return ISDF_E_HIP;
+    const BwdSplits sp_phi = bwd_splits(rows, n1, n_mu, n_phi, !tbar, P.slots);
+    const BwdSplits sp_psi = bwd_splits(rows, n1, n_mu, n_psi, !tbar, P.slots);
     if (!tbar) {
       // H += G^T diag(g) G (lower tiles, split-K, fixed-order reduction)
-      const int64_t tiles = gemm_tiles((int)ceil_div(n1, 128), (int)ceil_div(n1, 128), 1);
-      const int sp = splits_for(tiles, rows);
+      const int sp = sp_phi.h;
       const int64_t pn = (int64_t)n1 * n1;
       if (!tgemm<double, XC, XC>(n1, n1, rows, P.G, n1, P.G, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
         return ISDF_E_HIP;
@@ -463,8 +511,7 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       const int64_t ldt = aliased ? ld_tbar : 2 * ld_tbar;
       if (!dgemm<KC, KC, double, TT>(rows, n1, n1, tbar + r * ldt, ldt, minv, n1, P.G, n1, 1.0, 0.0, 0, ab, s))
         return ISDF_E_HIP;
-      const int64_t tiles = ceil_div(n1, 128) * ceil_div(n1, 128);
-      const int sp = splits_for(tiles, rows);
+      const int sp = sp_phi.h;
       const int64_t pn = (int64_t)n1 * n1;
       if (!tgemm<double, XC, XC>(n1, n1, rows, P.Th, n1, P.G, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn))
         return ISDF_E_HIP;
@@ -482,10 +529,10 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                          aliased ? 0 : 1);
     }
     if (!orbital_block<PREC, TS>(Abar, n_mu, Fphi, P.ap.f_phi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi,
-                                 P.Qpart, P.sc + 4, P.ap, ab, s))
+                                 P.Qpart, P.sc + 4, P.ap, sp_phi.q, ab, s))
       return ISDF_E_HIP;
     if (!aliased && !orbital_block<PREC, TS>(Bbar, n_mu, Fpsi, P.ap.f_psi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows,
-                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, ab, s))
+                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, sp_psi.q, ab, s))
       return ISDF_E_HIP;
   }
   if (!tbar) {
@@ -523,7 +570,11 @@ using namespace isdf;
 extern "C" size_t isdf_fit_backward_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
                                               int32_t aliased, isdf_prec prec, int64_t rblock) {
   if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
-  return plan_bwd(nullptr, 0, n_mu, n_phi, n_psi, aliased != 0, prec, rblock).bytes;
+  for (int a = 0; a < 3; ++a)
+    if (grid->n[a] <= 0) return 0;
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  if (rblock > nr) rblock = nr;
+  return plan_bwd(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, prec, rblock, device_slots()).bytes;
 }
 
 extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
@@ -542,7 +593,7 @@ extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const voi
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
   if (!aliased && dphi == dpsi) return ISDF_E_ARG;
   if (rblock > nr) rblock = nr;
-  BwdPlan P = plan_bwd(ws, ws_bytes, n_mu, n_phi, n_psi, aliased, prec, rblock);
+  BwdPlan P = plan_bwd(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, prec, rblock, device_slots());
   if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 #define ISDF_BWD_ARGS(TS)                                                                                        \
