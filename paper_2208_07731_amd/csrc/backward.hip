@@ -171,12 +171,28 @@ __global__ void mirror_lower(double* __restrict__ H, int n, const int* abort) {
   }
 }
 
-__global__ void add_loss(FitState* st, const double* __restrict__ partial, int n) {
+// loss += sum of the per-tile partials, in a fixed order (one workgroup of
+// 256 threads, four independent loads in flight per thread).
+constexpr int LOSS_THREADS = 256;
+__global__ __launch_bounds__(LOSS_THREADS) void add_loss(FitState* st, const double* __restrict__ partial, int n) {
+  __shared__ double red[LOSS_THREADS / ISDF_WAVE];
   if (st->abort) return;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += ISDF_WAVE) s += partial[i];
-  s = wave_sum(s);
-  if (threadIdx.x == 0) st->loss += s;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 3 * LOSS_THREADS < n; i += 4 * LOSS_THREADS) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += partial[i + u * LOSS_THREADS];
+  }
+  for (int u = 0; i < n; i += LOSS_THREADS, ++u) s[u] += partial[i];
+  double t = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
+  if ((threadIdx.x & (ISDF_WAVE - 1)) == 0) red[threadIdx.x / ISDF_WAVE] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < LOSS_THREADS / ISDF_WAVE; ++w) a += red[w];
+    st->loss += a;
+  }
 }
 
 // Corrections at the interpolation rows from Mbar = -combine(P):
@@ -503,7 +519,7 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                                                                              s))
         return ISDF_E_HIP;
       const int ltiles = (int)(ceil_div(rows, 128) * ceil_div(n1, 128));
-      hipLaunchKernelGGL(add_loss, dim3(1), dim3(ISDF_WAVE), 0, s, P.st, (const double*)P.lpart, ltiles);
+      hipLaunchKernelGGL(add_loss, dim3(1), dim3(LOSS_THREADS), 0, s, P.st, (const double*)P.lpart, ltiles);
       if (!launch_ok()) return ISDF_E_HIP;
     } else {
       // Theta = G M^-1, S = Thetabar M^-1 (over G), P += Theta^T S, Abar / Bbar in place
