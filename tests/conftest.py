@@ -17,3 +17,13 @@ def pytest_configure(config):
 def water8():
     import synth
     return synth.make_workload("water8")
+
+
+@pytest.fixture(scope="session")
+def golden_theta():
+    """Hand-derived Theta cases of tests/golden/theta_identity_rows.txt."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("golden_load", os.path.join(ROOT, "tests", "golden", "load.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.theta_identity_rows()

@@ -99,6 +99,21 @@ def test_fit_fp64_complex_swap_conjugates():
     assert rel(b.cpu().numpy(), a.cpu().numpy().conj()) <= 1e-11
 
 
+def test_fit_matches_hand_derived_golden(golden_theta):
+    """Hand-derived Theta (identity interpolation rows) through the C ABI, in
+    FP64 and the split precisions (whose parts represent these small integers
+    exactly)."""
+    for name, c in golden_theta.items():
+        for prec in ("fp64", "fp32", "bf16x6", "fp16x3"):
+            t = dev(np.concatenate([c["phi"], c["psi"]], axis=1))
+            phi_t = t[:, :2]
+            psi_t = phi_t if name == "aliased" else t[:, 2:]
+            th, _, info = isdf.fit(phi_t, psi_t, dev(c["idx"]), grid=(4, 1, 1), prec=prec)
+            got = th.cpu().numpy()
+            ref = c["theta"].real if name == "aliased" else c["theta"]
+            assert np.max(np.abs(got - ref)) <= 1e-14, (name, prec)
+
+
 @pytest.fixture(scope="module")
 def sio2_case():
     """SiO2-like workload (72^3 grid, N_phi = 192, N_psi = 384 sharing the

@@ -432,3 +432,11 @@ def test_kmeans_zero_weight_cluster_keeps_centroid():
     assert km["idx"][0] == 0
     m = pts.sum(axis=1) > 7.5
     assert np.allclose(km["centroids"][1], pts[m].mean(axis=0), rtol=1e-14)
+
+
+def test_fit_matches_hand_derived_golden(golden_theta):
+    """Theta = Phi . conj(Psi) when the interpolation rows are the identity
+    (derivation in tests/golden/theta_identity_rows.txt)."""
+    for name, c in golden_theta.items():
+        th = oracle.fit_theta(c["phi"], c["psi"], c["idx"])
+        assert np.max(np.abs(th - c["theta"])) <= 1e-15, name
