@@ -49,8 +49,8 @@ import scipy.linalg as sla
 __all__ = [
     "WEIGHT_KINDS", "weight", "grid_points", "metric_scale", "sqdist",
     "assign", "update", "snap", "kmeans", "gather", "gram_blocks", "hadamard",
-    "fit", "fit_theta", "fit_backward", "fit_residual", "cc_condition",
-    "explicit_z",
+    "fit", "fit_theta", "fit_backward", "fit_residual", "cluster_residual",
+    "cc_condition", "explicit_z",
 ]
 
 # --------------------------------------------------------------------------
@@ -298,6 +298,29 @@ def fit_residual(phi, psi, idx, theta=None) -> float:
     rp = (phi.real ** 2 + phi.imag ** 2).sum(axis=1)
     rs = (psi.real ** 2 + psi.imag ** 2).sum(axis=1)
     return float(np.dot(rp, rs) - np.real(np.sum(f["G"].conj() * th)))
+
+
+def cluster_residual(phi: np.ndarray, psi: np.ndarray, labels: np.ndarray, idx: np.ndarray) -> float:
+    """Appendix A, eqs. errorISDF and proj: the residual of representing
+    every row Z(r) by its projection on the row of its cluster's
+    interpolation point, R = sum_mu sum_{r in C_mu} ||Z(r) - proj Z(r)||^2,
+    with proj Z(r) = (Z(r) . Z*(r_mu)) / (Z(r_mu) . Z*(r_mu)) Z(r_mu).
+
+    Without forming Z (eq. Zmu and the first lines of eq. error2):
+    Z(r) . Z*(r') = (Phi(r) . Phi*(r')) conj(Psi(r) . Psi*(r')), so
+    Z(r) . Z*(r) = rho_phi(r) rho_psi(r) and each term is
+    rho_phi(r) rho_psi(r) - |Z(r) . Z*(r_mu)|^2 / (rho_phi(r_mu) rho_psi(r_mu)).
+    """
+    labels = np.asarray(labels)
+    idx = np.asarray(idx)
+    p = idx[labels]                                    # interpolation point of each row's cluster
+    rp = (phi.real ** 2 + phi.imag ** 2).sum(axis=1)   # rho_phi
+    rs = (psi.real ** 2 + psi.imag ** 2).sum(axis=1)   # rho_psi
+    a = np.sum(phi * phi[p].conj(), axis=1)            # Phi(r) . Phi*(r_mu)
+    b = np.sum(psi * psi[p].conj(), axis=1)            # Psi(r) . Psi*(r_mu)
+    zz = a * b.conj()                                  # Z(r) . Z*(r_mu)
+    terms = rp * rs - (zz.real ** 2 + zz.imag ** 2) / (rp[p] * rs[p])
+    return float(np.sum(terms))
 
 
 def explicit_z(phi: np.ndarray, psi: np.ndarray) -> np.ndarray:

@@ -322,6 +322,46 @@ def test_fit_residual_formula():
     assert abs(oracle.fit_residual(phi, psi, idx) - ref) <= 1e-11 * np.linalg.norm(Z) ** 2
 
 
+def test_cluster_residual_against_explicit_projection():
+    """Appendix A residual R by its definition (eqs. errorISDF, proj) on an
+    explicit Z: each row minus its projection on its cluster's interpolation
+    row; clusters from a real K-means run on a tiny grid."""
+    rng = np.random.default_rng(31)
+    n = 5
+    x = rng.standard_normal((n ** 3, 7)) + 1j * rng.standard_normal((n ** 3, 7))
+    y = rng.standard_normal((n ** 3, 4)) + 1j * rng.standard_normal((n ** 3, 4))
+    w = oracle.weight(x, y)
+    c0 = oracle.grid_points(n)[rng.choice(n ** 3, 9, replace=False)]
+    km = oracle.kmeans(n, w, c0, 5)
+    Z = oracle.explicit_z(x, y)
+    ref = 0.0
+    for r in range(n ** 3):
+        zm = Z[km["idx"][km["labels"][r]]]
+        proj = (Z[r] @ zm.conj()) / (zm @ zm.conj()) * zm
+        ref += np.linalg.norm(Z[r] - proj) ** 2
+    got = oracle.cluster_residual(x, y, km["labels"], km["idx"])
+    assert abs(got - ref) <= 1e-12 * np.linalg.norm(Z) ** 2
+
+
+def test_cluster_residual_bounds_and_limits():
+    """R >= the least-squares residual (the cluster projection is one
+    particular Theta supported on the interpolation rows); R = 0 when every
+    point is its own interpolation point; R scales as 4^(2k) under
+    Phi, Psi -> 2^k Phi, 2^k Psi."""
+    phi, psi, idx = tiny_case(12, n_r=60)
+    # clusters: every row to the interpolation point nearest in Z-row angle
+    Z = oracle.explicit_z(phi, psi)
+    zi = Z[idx]
+    cos = np.abs(Z @ zi.conj().T) / (np.linalg.norm(Z, axis=1)[:, None] * np.linalg.norm(zi, axis=1)[None, :])
+    labels = np.argmax(cos, axis=1).astype(np.int32)
+    labels[idx] = np.arange(len(idx))
+    R = oracle.cluster_residual(phi, psi, labels, idx)
+    assert R >= oracle.fit_residual(phi, psi, idx) * (1 - 1e-12)
+    everyone = np.arange(phi.shape[0])
+    assert abs(oracle.cluster_residual(phi, psi, everyone, everyone)) <= 1e-13 * np.linalg.norm(Z) ** 2
+    assert oracle.cluster_residual(2 * phi, 2 * psi, labels, idx) == 16 * R
+
+
 def test_fit_not_pd_raises():
     """A duplicated interpolation point makes C C^H singular: reported, not
     regularised."""
