@@ -107,6 +107,39 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int) -> dict:
     return out
 
 
+def weight_study(phi, psi, wl, d, kinds) -> dict:
+    """K-means with each weight function (eq. weight function for PSM, eq.
+    weight function 2 for alpha = 1..4), then the FP64 fit: the relative
+    least-squares residual ||Z - Theta C|| / ||Z|| and Appendix A's cluster
+    residual R / ||Z||^2 for each (the paper's SSM-vs-PSM comparison, on these
+    synthetic orbitals).  Empty clusters are dropped before the fit."""
+    import math
+
+    import torch
+
+    from paper_2208_07731_amd import api
+
+    out = {}
+    for kind in kinds:
+        t0 = time.perf_counter()
+        r = api.kmeans(phi, None if wl.aliased else psi, wl.n_mu, d["c0"], wl.kmeans_iters, grid=wl.n, weight=kind)
+        live = r.idx >= 0
+        lut = torch.cumsum(live.to(torch.int32), 0, dtype=torch.int32) - 1
+        idx = r.idx[live].contiguous()
+        labels = lut[r.labels.long()].to(torch.int32).contiguous()
+        _, minv, info = api.fit(phi, None if wl.aliased else psi, idx, nrows=0)
+        res, zz = api.fit_residual(phi, None if wl.aliased else psi, idx, minv, rblock=wl.rblock or None)
+        R = api.cluster_residual(phi, None if wl.aliased else psi, labels, idx)
+        out[kind] = {"n_mu": int(idx.numel()), "kmeans_rounds": r.info["iters"],
+                     "ls_rel_residual": math.sqrt(max(res, 0.0) / zz), "cluster_residual_rel": R / zz,
+                     "cc_pivot_ratio": info["pivot_max"] / info["pivot_min"] if info["pivot_min"] > 0 else None,
+                     "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] weight {kind}: {out[kind]}")
+        del minv
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(d, idx, iters_run: int) -> dict:
     """The FP64 oracle on a bounded sample of the same workload, scaled to
     one full step (ms): weight at full size, two K-means rounds at full size
@@ -170,6 +203,8 @@ def main():
     ap.add_argument("--mixed", default="bf16x6,fp16x3,fp32",
                     help="comma-separated orbital-contraction precisions to time beside --prec ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weight-study", default="",
+                    help="comma-separated weight functions (ssm,psm,sm,scm,sqm) to compare by fit residuals")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -274,6 +309,8 @@ def main():
             del st2
             torch.cuda.empty_cache()
         del theta64
+    if args.weight_study:
+        out["weight_study"] = weight_study(phi, psi, wl, d, [k for k in args.weight_study.split(",") if k])
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         c0 = np.asarray(d["c0"], dtype=np.int64)  # seeds are distinct grid points

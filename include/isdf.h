@@ -244,6 +244,46 @@ int isdf_fit_backward(const isdf_grid* grid /* host */, isdf_dtype dt,
                       double* loss, int64_t rblock,
                       isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ----------------------------------------------------------- residuals */
+/*
+ * Least-squares residual of the fit without forming Z (follows from
+ * eq. theta: Theta C C^H = Z C^H, so ||Theta C||^2 = Re sum conj(Z C^H) . Theta):
+ *   out[0] = ||Z - Theta C||_F^2 = sum_r rho_phi(r) rho_psi(r) - Re sum conj(Z C^H) . Theta
+ *   out[1] = ||Z||_F^2          = sum_r rho_phi(r) rho_psi(r)
+ * with rho_phi = sum_i |phi_i|^2, rho_psi = sum_j |psi_j|^2, Theta the fit of
+ * minv (as left by isdf_fit with ISDF_FIT_FACTOR on the same inputs), Z C^H in
+ * precision `prec`, Theta and the sums in FP64.  out: device, 2 doubles.
+ * Runs r-block by r-block (rblock rows); workspace: isdf_fit_residual_workspace
+ * bytes.  Sums are in a fixed order (reproducible bit for bit).
+ */
+size_t isdf_fit_residual_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                                   int32_t aliased, isdf_prec prec, int64_t rblock);
+int isdf_fit_residual(const isdf_grid* grid /* host */, isdf_dtype dt,
+                      const void* phi, int64_t ld_phi, int32_t n_phi,
+                      const void* psi, int64_t ld_psi, int32_t n_psi,
+                      const int32_t* idx, int32_t n_mu, isdf_prec prec,
+                      const double* minv, int64_t rblock, double* out,
+                      isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Cluster residual of Appendix A (eqs. errorISDF and proj): every row Z(r)
+ * replaced by its projection on the row of its cluster's interpolation point
+ * p = idx[labels[r]],
+ *   out[0] = R = sum_r [ rho_phi(r) rho_psi(r) - |Z(r) . Z*(p)|^2 / (rho_phi(p) rho_psi(p)) ],
+ *   Z(r) . Z*(p) = (Phi(r) . Phi*(p)) conj(Psi(r) . Psi*(p))   (eq. Zmu),
+ *   out[1] = number of rows skipped because labels[r] is outside [0, n_mu)
+ *            or idx[labels[r]] is outside the grid,
+ * labels [N_r] and idx [n_mu] as left by isdf_kmeans.  out: device, 2
+ * doubles; workspace: isdf_cluster_residual_workspace() bytes.  FP64 sums in
+ * a fixed order.
+ */
+size_t isdf_cluster_residual_workspace(void);
+int isdf_cluster_residual(const isdf_grid* grid /* host */, isdf_dtype dt,
+                          const void* phi, int64_t ld_phi, int32_t n_phi,
+                          const void* psi, int64_t ld_psi, int32_t n_psi,
+                          const int32_t* labels, const int32_t* idx, int32_t n_mu, double* out,
+                          void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* isdf_version(void);
 const char* isdf_strerror(int status);

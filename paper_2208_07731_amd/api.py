@@ -233,3 +233,52 @@ def fit_backward(phi: torch.Tensor, psi: torch.Tensor | None, idx: torch.Tensor,
     if aliased:
         dpsi = dphi.clone()
     return dphi, dpsi, loss, d
+
+
+def fit_residual(phi: torch.Tensor, psi: torch.Tensor | None, idx: torch.Tensor, minv: torch.Tensor, *,
+                 prec: str = "fp64", rblock: int | None = None, grid=None) -> tuple[float, float]:
+    """(||Z - Theta C||_F^2, ||Z||_F^2) for the fit of minv (isdf_fit_residual)."""
+    lib = L.load()
+    psi, dt, pp, lp, npf, ps, lps, nps, aliased = _fit_common(phi, psi, idx)
+    n_r, n_mu = phi.shape[0], idx.numel()
+    g = _grid(grid, n_r, (1.0, 1.0, 1.0), geometry=False)
+    rblock = min(n_r, 1 << 17) if rblock is None else rblock
+    p = _prec(prec)
+    dev = phi.device
+    if minv.dtype != torch.float64 or minv.numel() < lib.isdf_fit_minv_elems(n_mu, int(aliased)):
+        raise ValueError("minv too small or not float64")
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    info = torch.zeros(C.sizeof(L.FitInfo), dtype=torch.uint8, device=dev)
+    wsb = lib.isdf_fit_residual_workspace(C.byref(g), n_mu, npf, nps, int(aliased), p, rblock)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    code = lib.isdf_fit_residual(C.byref(g), dt, pp, lp, npf, ps, lps, nps, idx.data_ptr(), n_mu, p,
+                                 minv.data_ptr(), rblock, out.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                 _stream_handle())
+    _check(code, "isdf_fit_residual")
+    torch.cuda.current_stream().synchronize()
+    inf = _read_struct(info, L.FitInfo)
+    if inf.status != L.OK:
+        raise ISDFError(inf.status, "isdf_fit_residual")
+    r = out.cpu().tolist()
+    return r[0], r[1]
+
+
+def cluster_residual(phi: torch.Tensor, psi: torch.Tensor | None, labels: torch.Tensor, idx: torch.Tensor, *,
+                     grid=None) -> float:
+    """Appendix A cluster residual R for K-means labels and interpolation
+    points (isdf_cluster_residual); raises if any row had an invalid label."""
+    lib = L.load()
+    psi, dt, pp, lp, npf, ps, lps, nps, aliased = _fit_common(phi, psi, idx)
+    n_r, n_mu = phi.shape[0], idx.numel()
+    if labels.dtype != torch.int32 or not labels.is_contiguous() or labels.numel() != n_r:
+        raise TypeError("labels must be a contiguous int32 tensor of N_r entries")
+    g = _grid(grid, n_r, (1.0, 1.0, 1.0), geometry=False)
+    out = torch.zeros(2, dtype=torch.float64, device=phi.device)
+    ws = torch.empty(lib.isdf_cluster_residual_workspace(), dtype=torch.uint8, device=phi.device)
+    code = lib.isdf_cluster_residual(C.byref(g), dt, pp, lp, npf, ps, lps, nps, labels.data_ptr(), idx.data_ptr(),
+                                     n_mu, out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
+    _check(code, "isdf_cluster_residual")
+    r = out.cpu().tolist()
+    if r[1] != 0:
+        raise ValueError(f"{int(r[1])} rows have a label outside [0, n_mu) or an invalid interpolation point")
+    return r[0]

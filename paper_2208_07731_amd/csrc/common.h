@@ -66,6 +66,59 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// Fixed-order reductions of per-workgroup pairs (deterministic run to run).
+constexpr int PAIR_THREADS = 256;
+
+// Sums (a, b) over the workgroup (waves in order) into part[2 blockIdx.x + {0, 1}].
+__device__ __forceinline__ void block_pair_store(double a, double b, double* part) {
+  __shared__ double red[2][PAIR_THREADS / ISDF_WAVE];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x / ISDF_WAVE;
+  if ((threadIdx.x & (ISDF_WAVE - 1)) == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int i = 0; i < (int)(blockDim.x / ISDF_WAVE); ++i) {
+      sa += red[0][i];
+      sb += red[1][i];
+    }
+    part[2 * blockIdx.x] = sa;
+    part[2 * blockIdx.x + 1] = sb;
+  }
+}
+
+// out[0] = sum_i part[2 i], out[1] = sum_i part[2 i + 1] (one workgroup).
+static __global__ __launch_bounds__(PAIR_THREADS) void sum_pairs(const double* __restrict__ part, int n,
+                                                           double* __restrict__ out) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += PAIR_THREADS) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  __shared__ double red[2][PAIR_THREADS / ISDF_WAVE];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x / ISDF_WAVE;
+  if ((threadIdx.x & (ISDF_WAVE - 1)) == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int i = 0; i < PAIR_THREADS / ISDF_WAVE; ++i) {
+      sa += red[0][i];
+      sb += red[1][i];
+    }
+    out[0] = sa;
+    out[1] = sb;
+  }
+}
+
 // Positive doubles order like their bit patterns: atomic min/max on them.
 __device__ __forceinline__ void atomic_min_pos(double* p, double v) {
   atomicMin((unsigned long long*)p, (unsigned long long)__double_as_longlong(v));

@@ -33,11 +33,15 @@ struct FitPlan {
   InvWork inv;
   double* G;
   SplitWork sw;
+  double* Th;    // residual mode: Theta of one r-block (FP64)
+  double* part;  // residual mode: per-workgroup (||Z||^2 - Re G.Theta, ||Z||^2) pairs
   size_t bytes;
 };
 
+constexpr int RESID_BLOCKS = 512;  // workgroups per r-block of the residual reduction
+
 static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, int n_psi, bool aliased,
-                        isdf_prec prec, int64_t rblock) {
+                        isdf_prec prec, int64_t rblock, bool resid = false) {
   const size_t tsize = tsize_of(prec);
   Carver c(ws, cap);
   FitPlan P{};
@@ -53,8 +57,49 @@ static FitPlan plan_fit(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   P.inv.R = c.take<double>((size_t)n1 * n1);
   P.G = c.take<double>((size_t)rblock * n1);
   P.sw = carve_split(c, prec, n_phi, n_psi, aliased, n_mu, rblock > n_mu ? rblock : n_mu);
+  if (resid) {
+    P.Th = c.take<double>((size_t)rblock * n1);
+    P.part = c.take<double>((size_t)2 * RESID_BLOCKS * ceil_div(nr, rblock));
+  }
   P.bytes = c.used;
   return P;
+}
+
+// Residual terms of rows [r0, r0 + rows): per row, with G and Theta read as
+// n1 reals (Re G conj(Theta) summed over nu is their dot product),
+// ||Z(r)||^2 = rho_phi(r) rho_psi(r); pairs (||Z(r)||^2 - dot, ||Z(r)||^2)
+// summed per workgroup into part.
+template <class TS>
+__global__ __launch_bounds__(PAIR_THREADS) void fit_resid_rows(const double* __restrict__ G,
+                                                               const double* __restrict__ Th, int rows, int n1,
+                                                               const TS* __restrict__ phi, int64_t ldp, int nphi,
+                                                               const TS* __restrict__ psi, int64_t lds, int npsi,
+                                                               int aliased, int64_t r0, double* __restrict__ part) {
+  const int lane = threadIdx.x & (ISDF_WAVE - 1);
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / ISDF_WAVE;
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / ISDF_WAVE;
+  double acc = 0.0, zz = 0.0;
+  for (int64_t q = wave; q < rows; q += nwaves) {
+    double dot = 0.0, rp = 0.0, rs = 0.0;
+    for (int k = lane; k < n1; k += ISDF_WAVE) dot += G[q * n1 + k] * Th[q * n1 + k];
+    const int64_t r = r0 + q;
+    for (int i = lane; i < nphi; i += ISDF_WAVE) {
+      const double2 z = Cplx<TS>::load(phi + 2 * (r * ldp + i));
+      rp += z.x * z.x + z.y * z.y;
+    }
+    if (!aliased)
+      for (int j = lane; j < npsi; j += ISDF_WAVE) {
+        const double2 z = Cplx<TS>::load(psi + 2 * (r * lds + j));
+        rs += z.x * z.x + z.y * z.y;
+      }
+    dot = wave_sum(dot);
+    rp = wave_sum(rp);
+    rs = aliased ? rp : wave_sum(rs);
+    acc += rp * rs - dot;
+    zz += rp * rs;
+  }
+  if (lane != 0) acc = zz = 0.0;
+  block_pair_store(acc, zz, part);
 }
 
 template <int PREC, class TS, class TT>
@@ -100,9 +145,88 @@ static int fit_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   return ISDF_OK;
 }
 
+// ||Z - Theta C||_F^2 and ||Z||_F^2 for the Theta of (C C^H)^-1 = minv, r-block
+// by r-block: Gram + Hadamard, Theta = G minv (FP64), row terms, fixed-order sums.
+template <int PREC, class TS>
+static int resid_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                     bool aliased, const int32_t* idx, int n_mu, const double* minv, int64_t rblock, double* out,
+                     isdf_fit_info* info, const FitPlan& P, hipStream_t s) {
+  const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
+  const int n1 = aliased ? n_mu : 2 * n_mu;
+  const int* ab = &P.st->abort;
+  typedef typename Prec<PREC>::E T;
+  hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
+  if (!launch_ok()) return ISDF_E_HIP;
+  T* Ephi = (T*)P.Ephi;
+  T* Epsi = aliased ? Ephi : (T*)P.Epsi;
+  if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
+  if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
+  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
+  if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
+    return ISDF_E_HIP;
+  int64_t blk = 0;
+  for (int64_t r = 0; r < nr; r += rblock, ++blk) {
+    const int rows = (int)(nr - r < rblock ? nr - r : rblock);
+    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr, r, rows,
+                        P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, &P.sw))
+      return ISDF_E_HIP;
+    if (!dgemm<KC, KC, double>(rows, n1, n1, P.G, n1, minv, n1, P.Th, n1, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
+    hipLaunchKernelGGL((fit_resid_rows<TS>), dim3(RESID_BLOCKS), dim3(PAIR_THREADS), 0, s, (const double*)P.G,
+                       (const double*)P.Th, rows, n1, phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased ? 1 : 0, r,
+                       P.part + 2 * RESID_BLOCKS * blk);
+    if (!launch_ok()) return ISDF_E_HIP;
+  }
+  hipLaunchKernelGGL(sum_pairs, dim3(1), dim3(PAIR_THREADS), 0, s, (const double*)P.part,
+                     (int)(RESID_BLOCKS * blk), out);
+  hipLaunchKernelGGL(fit_finish, dim3(1), dim3(1), 0, s, P.st, info, (double*)nullptr, 0);
+  if (!launch_ok()) return ISDF_E_HIP;
+  return ISDF_OK;
+}
+
 }  // namespace isdf
 
 using namespace isdf;
+
+extern "C" size_t isdf_fit_residual_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                                              int32_t aliased, isdf_prec prec, int64_t rblock) {
+  if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  if (nr <= 0) return 0;
+  if (rblock > nr) rblock = nr;
+  return plan_fit(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, prec, rblock, true).bytes;
+}
+
+extern "C" int isdf_fit_residual(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+                                 int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx,
+                                 int32_t n_mu, isdf_prec prec, const double* minv, int64_t rblock, double* out,
+                                 isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream) {
+  int64_t nr = 0;
+  if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
+  if (!minv || !out || !info || rblock <= 0) return ISDF_E_ARG;
+  if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
+  if (rblock > nr) rblock = nr;
+  if (ceil_div(nr, rblock) * RESID_BLOCKS > INT32_MAX) return ISDF_E_ARG;
+  const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
+  FitPlan P = plan_fit(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, prec, rblock, true);
+  if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+#define ISDF_RES_ARGS(TS) \
+  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, minv, rblock, out, info, P, s
+  if (dt == ISDF_C128) {
+    switch (prec) {
+      case ISDF_P_FP64: return resid_run<ISDF_P_FP64, double>(ISDF_RES_ARGS(double));
+      case ISDF_P_FP32: return resid_run<ISDF_P_FP32, double>(ISDF_RES_ARGS(double));
+      case ISDF_P_BF16X6: return resid_run<ISDF_P_BF16X6, double>(ISDF_RES_ARGS(double));
+      default: return resid_run<ISDF_P_FP16X3, double>(ISDF_RES_ARGS(double));
+    }
+  }
+  switch (prec) {
+    case ISDF_P_FP32: return resid_run<ISDF_P_FP32, float>(ISDF_RES_ARGS(float));
+    case ISDF_P_BF16X6: return resid_run<ISDF_P_BF16X6, float>(ISDF_RES_ARGS(float));
+    default: return resid_run<ISDF_P_FP16X3, float>(ISDF_RES_ARGS(float));
+  }
+#undef ISDF_RES_ARGS
+}
 
 extern "C" size_t isdf_fit_minv_elems(int32_t n_mu, int32_t aliased) {
   if (n_mu <= 0) return 0;

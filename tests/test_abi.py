@@ -113,3 +113,24 @@ def test_fit_rejects_bad_arguments(case):
                         kw["row0"], kw["nrows"], FAKE, kw["ldt"], 512, FAKE, FAKE, kw["wsb"], None)
     expect = {"no_ws": L.E_WORKSPACE}.get(case, L.E_ARG)
     assert code == expect
+
+
+def test_residual_entry_points_reject_bad_arguments():
+    lib = L.load()
+    g = L.make_grid(8)
+    assert lib.isdf_cluster_residual_workspace() > 0
+    assert lib.isdf_fit_residual_workspace(C.byref(g), 5, 4, 4, 1, 0, 512) > 0
+    # cluster residual: missing labels, bad dtype, short workspace
+    assert lib.isdf_cluster_residual(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, None, FAKE, 5, FAKE, FAKE, 1 << 20,
+                                     None) == L.E_ARG
+    assert lib.isdf_cluster_residual(C.byref(g), 7, FAKE, 4, 4, FAKE, 4, 4, FAKE, FAKE, 5, FAKE, FAKE, 1 << 20,
+                                     None) == L.E_ARG
+    assert lib.isdf_cluster_residual(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, FAKE, FAKE, 5, FAKE, FAKE, 8,
+                                     None) == L.E_WORKSPACE
+    # fit residual: no minv, FP64 on c64 storage, short workspace
+    assert lib.isdf_fit_residual(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, 0, None, 512, FAKE, FAKE, FAKE,
+                                 1 << 30, None) == L.E_ARG
+    assert lib.isdf_fit_residual(C.byref(g), L.C64, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, 0, FAKE, 512, FAKE, FAKE, FAKE,
+                                 1 << 30, None) == L.E_ARG
+    assert lib.isdf_fit_residual(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, 0, FAKE, 512, FAKE, FAKE, FAKE,
+                                 16, None) == L.E_WORKSPACE
