@@ -203,6 +203,8 @@ def main():
     ap.add_argument("--mixed", default="bf16x6,fp16x3,fp32",
                     help="comma-separated orbital-contraction precisions to time beside --prec ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the step as replays of one captured HIP graph (phases still from eager steps)")
     ap.add_argument("--weight-study", default="",
                     help="comma-separated weight functions (ssm,psm,sm,scm,sqm) to compare by fit residuals")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -242,6 +244,28 @@ def main():
         log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
         del src, dst
 
+    def run_graph(st, steps):
+        """The step captured once as a HIP graph and replayed `steps` times."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            st.enqueue()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            st.enqueue()
+        graph.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        st.check()
+        return a.elapsed_time(b) / steps
+
     def run(prec, steps, warmup):
         st = ISDFStep(phi, None if wl.aliased else psi, wl.n_mu, d["c0"], wl.kmeans_iters, g=g, prec=prec,
                       rblock=rblock, block_rows=block_rows, keep_theta=block_rows is None)
@@ -266,6 +290,9 @@ def main():
         el = lambda i: sum(p[i].elapsed_time(p[i + 1]) for p in phases) / steps  # noqa: E731
         ph = {"kmeans": round(el(0), 3), "factor": round(el(1), 3), "zc": round(zc_ms, 3),
               "solve": round(solve_ms, 3), "adjoint": round(el(3), 3)}
+        if args.graph:
+            ph["eager_step"] = round(total, 3)
+            total = run_graph(st, steps)
         return st, total, solve_ms / nb, ph, info
 
     log(f"[bench] {args.prec}: warmup {args.warmup}, timing {args.steps} steps")

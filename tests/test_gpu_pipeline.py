@@ -1,0 +1,90 @@
+"""The preallocated whole-step form (ISDFStep): against the one-shot API and
+the oracle, in streamed row blocks, and replayed from a captured HIP graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+isdf = pytest.importorskip("paper_2208_07731_amd")
+from paper_2208_07731_amd.pipeline import ISDFStep  # noqa: E402
+
+EPS = np.finfo(np.float64).eps
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def water8_step(water8):
+    phi = water8["phi"]
+    wl = water8["wl"]
+    g = np.random.default_rng(1004).uniform(0.5, 1.5, wl.n_r)
+    return dict(phi=phi, wl=wl, g=g, c0=water8["c0"], phi_t=dev(phi), g_t=dev(g))
+
+
+def run_step(s, **kw):
+    st = ISDFStep(s["phi_t"], None, s["wl"].n_mu, s["c0"], s["wl"].kmeans_iters, g=s["g_t"], **kw)
+    st.enqueue()
+    info = st.check()
+    return st, info
+
+
+def test_step_matches_oracle(water8_step):
+    s = water8_step
+    st, info = run_step(s)
+    wl = s["wl"]
+    km = oracle.kmeans(wl.n, oracle.weight(s["phi"], s["phi"]), s["c0"], wl.kmeans_iters)
+    assert np.array_equal(st.idx.cpu().numpy(), km["idx"])
+    ref = oracle.fit_backward(s["phi"], s["phi"], km["idx"], g=s["g"])
+    th = oracle.fit_theta(s["phi"], s["phi"], km["idx"]).real
+    kappa = oracle.cc_condition(s["phi"], s["phi"], km["idx"])
+    got = st.theta.cpu().numpy()
+    assert np.linalg.norm(got - th) / np.linalg.norm(th) <= max(1e-12, 4 * kappa * EPS)
+    dphi = st.dphi.cpu().numpy()
+    assert np.linalg.norm(dphi - ref["dphi"]) / np.linalg.norm(ref["dphi"]) <= max(1e-11, 100 * kappa * EPS)
+    assert abs(st.loss.item() - ref["loss"]) <= 1e-10 * ref["loss"]
+
+
+def test_streamed_blocks_equal_one_block(water8_step):
+    """Z C^H and Theta in ragged row blocks give Theta bit for bit."""
+    s = water8_step
+    one, _ = run_step(s)
+    blk, _ = run_step(s, block_rows=5000)
+    assert len(blk.blocks) == 3
+    assert torch.equal(one.theta, blk.theta)
+    assert torch.equal(one.dphi, blk.dphi)
+
+
+def test_graph_replay_matches_eager(water8_step):
+    """The whole step captured once and replayed three times, with eager work
+    and synchronisation between replays: every replay reproduces the eager
+    outputs bit for bit (every kernel, no memset nodes)."""
+    s = water8_step
+    st, _ = run_step(s)
+    ref = {k: getattr(st, k).clone() for k in ("idx", "theta", "dphi", "loss", "w", "labels")}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        st.enqueue()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        st.enqueue()
+    for rep in range(3):
+        for k in ("theta", "dphi", "w", "labels"):
+            getattr(st, k).fill_(-7)
+        st.loss.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            assert torch.equal(getattr(st, k), v), (rep, k)
+        # eager work between replays
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(x)
