@@ -59,6 +59,11 @@ class ISDFStep:
         self.fit_info = torch.zeros(C.sizeof(L.FitInfo), dtype=u8, device=dev)
         self.fit_ws = torch.empty(self.lib.isdf_fit_workspace(C.byref(self.grid), n_mu, self.npf, self.nps,
                                                               int(self.aliased), self.prec, 1), dtype=u8, device=dev)
+        # the factorisation runs on a second stream, beside Z C^H (they only
+        # meet at the first solve); default priority like every other stream
+        self.side = torch.cuda.Stream(device=dev)
+        self.ev_km = torch.cuda.Event()
+        self.ev_factor = torch.cuda.Event()
         self.block_rows = n_r if block_rows is None else min(int(block_rows), n_r)
         self.blocks = [(r, min(self.block_rows, n_r - r)) for r in range(0, n_r, self.block_rows)]
         self.keep_theta = keep_theta or len(self.blocks) == 1
@@ -85,13 +90,16 @@ class ISDFStep:
         if code != L.OK:
             raise ISDFError(code, where)
 
-    def enqueue(self, block_events=None, phase_events=None):
-        """Enqueue the step on the current stream.  block_events (one triple
-        of events per row block) bracket each block's Z C^H and Theta
-        launches; phase_events (5 events) are recorded before K-means and
-        after K-means, the factorisation, the last Theta block and the
-        adjoint."""
-        lib, s = self.lib, torch.cuda.current_stream().cuda_stream
+    def enqueue(self, block_events=None, phase_events=None, factor_events=None):
+        """Enqueue the step on the current stream (the factorisation of C C^H
+        forks onto a second stream right after K-means and joins back before
+        the first solve).  block_events (one triple of events per row block)
+        bracket each block's Z C^H and Theta launches; phase_events (5 events)
+        are recorded before K-means and after K-means, the fork, the last
+        Theta block and the adjoint; factor_events (2) bracket the
+        factorisation on its own stream."""
+        main = torch.cuda.current_stream()
+        lib, s = self.lib, main.cuda_stream
         gp = C.byref(self.grid)
         ph = phase_events or [None] * 5
 
@@ -106,10 +114,17 @@ class ISDFStep:
                                    self.km_info.data_ptr(), self.km_ws.data_ptr(), self.km_ws.numel(), s),
                    "isdf_kmeans")
         mark(1)
+        self.ev_km.record(main)
+        self.side.wait_event(self.ev_km)
+        if factor_events:
+            factor_events[0].record(self.side)
         self._call(lib.isdf_fit(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
                                 self.idx.data_ptr(), self.n_mu, self.prec, self.minv.data_ptr(), L.FIT_FACTOR, 0, 0,
                                 None, self.n_mu, 1, self.fit_info.data_ptr(), self.fit_ws.data_ptr(),
-                                self.fit_ws.numel(), s), "isdf_fit")
+                                self.fit_ws.numel(), self.side.cuda_stream), "isdf_fit")
+        if factor_events:
+            factor_events[1].record(self.side)
+        self.ev_factor.record(self.side)
         mark(2)
         esz = self.theta.element_size()
         for b, (r0, nrows) in enumerate(self.blocks):
@@ -121,6 +136,8 @@ class ISDFStep:
                                    self.zc_ws.data_ptr(), self.zc_ws.numel(), s), "isdf_zc")
             if be:
                 be[1].record()
+            if b == 0:
+                main.wait_event(self.ev_factor)
             th = self.theta.data_ptr() + (r0 * self.n_mu * esz if self.keep_theta else 0)
             self._call(lib.isdf_apply_minv(self.n_mu, int(self.aliased), self.minv.data_ptr(), self.G.data_ptr(),
                                            self.n1, nrows, self.dt, th, self.n_mu, s), "isdf_apply_minv")
