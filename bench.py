@@ -334,7 +334,7 @@ def main():
         for prec in [p for p in args.mixed.split(",") if p]:
             log(f"[bench] {prec}: timing")
             st2, ms2, _, ph2, _ = run(prec, args.steps, args.warmup)
-            err = float(torch.linalg.norm(st2.theta.double() - theta64) / torch.linalg.norm(theta64))
+            err = float(torch.linalg.norm(st2.theta.to(theta64.dtype) - theta64) / torch.linalg.norm(theta64))
             out["mixed"][prec] = {"ms_per_step": round(ms2, 3), "phases_ms": ph2,
                                   "zc": phase_rates(wl, prec, ph2, out["kmeans"]["rounds"])["zc"],
                                   "theta_rel_err_vs_fp64_gpu": err, "speedup_vs_fp64": round(ms / ms2, 3)}
