@@ -50,7 +50,7 @@ __all__ = [
     "WEIGHT_KINDS", "weight", "grid_points", "metric_scale", "sqdist",
     "assign", "update", "snap", "kmeans", "gather", "gram_blocks", "hadamard",
     "fit", "fit_theta", "fit_backward", "fit_residual", "cluster_residual",
-    "cc_condition", "explicit_z",
+    "cc_condition", "explicit_z", "reciprocal_sq", "poisson",
 ]
 
 # --------------------------------------------------------------------------
@@ -321,6 +321,29 @@ def cluster_residual(phi: np.ndarray, psi: np.ndarray, labels: np.ndarray, idx: 
     zz = a * b.conj()                                  # Z(r) . Z*(r_mu)
     terms = rp * rs - (zz.real ** 2 + zz.imag ** 2) / (rp[p] * rs[p])
     return float(np.sum(terms))
+
+
+def reciprocal_sq(n, h) -> np.ndarray:
+    """|G|^2 on the grid's reciprocal lattice, G_a = 2 pi m_a / (n_a h_a) with
+    m_a the FFT-order integers in [-n_a/2, n_a/2); shape (n0, n1, n2)."""
+    g = [2.0 * np.pi * np.fft.fftfreq(n[a], d=1.0 / n[a]) / (n[a] * h[a]) for a in range(3)]
+    return g[0][:, None, None] ** 2 + g[1][None, :, None] ** 2 + g[2][None, None, :] ** 2
+
+
+def poisson(theta: np.ndarray, n, h=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """V_mu(r) = int zeta_mu(r') / |r - r'| dr' (eq. V_mu) for every column
+    zeta_mu of theta [N_r][N_mu] on the periodic grid (p = (i n1 + j) n2 + k,
+    spacings h in Bohr): V-hat(G) = 4 pi zeta-hat(G) / |G|^2, with the G = 0
+    term dropped (a neutralising background; the paper does not state how the
+    periodic integral is regularised).  Same layout and dtype kind as theta."""
+    n = tuple(int(x) for x in (n if not np.isscalar(n) else (n, n, n)))
+    g2 = reciprocal_sq(n, h)
+    kern = np.zeros_like(g2)
+    kern[g2 > 0] = 4.0 * np.pi / g2[g2 > 0]
+    z = theta.reshape(n + (theta.shape[1],))
+    zh = np.fft.fftn(z, axes=(0, 1, 2))
+    v = np.fft.ifftn(zh * kern[..., None], axes=(0, 1, 2)).reshape(theta.shape)
+    return v.real.copy() if np.isrealobj(theta) else v
 
 
 def explicit_z(phi: np.ndarray, psi: np.ndarray) -> np.ndarray:

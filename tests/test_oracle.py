@@ -480,3 +480,42 @@ def test_fit_matches_hand_derived_golden(golden_theta):
     for name, c in golden_theta.items():
         th = oracle.fit_theta(c["phi"], c["psi"], c["idx"])
         assert np.max(np.abs(th - c["theta"])) <= 1e-15, name
+
+
+# --------------------------------------------------- V_mu (eq. V_mu, next step)
+def _plane_wave(n, h, m):
+    i, j, k = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    ph = 2 * np.pi * (m[0] * i / n[0] + m[1] * j / n[1] + m[2] * k / n[2])
+    gsq = sum((2 * np.pi * m[a] / (n[a] * h[a])) ** 2 for a in range(3))
+    return np.exp(1j * ph).reshape(-1), gsq
+
+
+def test_poisson_plane_waves_closed_form():
+    """A grid plane wave e^{iG.r} is an eigenfunction: V = 4 pi / |G|^2 e^{iG.r}
+    (anisotropic grid and spacings; positive and negative frequencies)."""
+    n, h = (6, 5, 8), (0.7, 1.1, 0.45)
+    cols, expect = [], []
+    for m in [(1, 0, 0), (0, -2, 1), (2, 2, -3), (-3, 1, 4)]:
+        z, gsq = _plane_wave(n, h, m)
+        cols.append(z)
+        expect.append(4 * np.pi / gsq * z)
+    V = oracle.poisson(np.stack(cols, axis=1), n, h)
+    assert np.max(np.abs(V - np.stack(expect, axis=1))) <= 1e-12
+
+
+def test_poisson_background_real_and_linear():
+    """Constant fields have no potential (G = 0 dropped); real fields give
+    real potentials equal to the real part of the complex transform; the
+    map is linear."""
+    rng = np.random.default_rng(51)
+    n, h = (4, 6, 5), (1.0, 0.8, 1.3)
+    nr = 4 * 6 * 5
+    c = np.full((nr, 1), 3.0 + 1.0j)
+    assert np.max(np.abs(oracle.poisson(c, n, h))) <= 1e-13
+    x = rng.standard_normal((nr, 3))
+    y = rng.standard_normal((nr, 3))
+    vx = oracle.poisson(x, n, h)
+    assert vx.dtype == np.float64
+    vxy = oracle.poisson(x + 1j * y, n, h)
+    assert np.max(np.abs(vxy.real - vx)) <= 1e-12 * np.max(np.abs(vx))
+    assert np.max(np.abs(vxy - vx - 1j * oracle.poisson(y, n, h))) <= 1e-12 * np.max(np.abs(vxy))
