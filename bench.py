@@ -110,6 +110,36 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int) -> dict:
     return out
 
 
+def poisson_leg(st, wl, steps) -> dict:
+    """V_mu for every column of the step's Theta (isdf_poisson), HIP-event
+    timed; algorithmic bytes: Theta read once and V written once, plus the
+    four intermediate passes over the complex work array (real Theta packs
+    two columns per complex signal)."""
+    import torch
+
+    from paper_2208_07731_amd import api
+
+    h = wl.box_angstrom / 0.529177 / wl.n
+    th = st.theta
+    api.poisson(th, wl.n, (h, h, h))
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        v = api.poisson(th, wl.n, (h, h, h))
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    cols = th.shape[1] if th.is_complex() else (th.shape[1] + 1) // 2
+    work = th.shape[0] * cols * 16
+    io = th.numel() * th.element_size()
+    nbytes = 2 * io + 8 * work  # 5 passes: Theta in, V out, 4 x (W in + W out) in between
+    del v
+    return {"ms": round(ms, 3), "bound": "hbm", "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
+            "frac": round(nbytes / ms / 1e6 / HBM_PEAK, 4), "columns": th.shape[1],
+            "note": "includes the per-call workspace allocation by the Python wrapper"}
+
+
 def weight_study(phi, psi, wl, d, kinds) -> dict:
     """K-means with each weight function (eq. weight function for PSM, eq.
     weight function 2 for alpha = 1..4), then the FP64 fit: the relative
@@ -208,6 +238,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="time the step as replays of one captured HIP graph (phases still from eager steps)")
+    ap.add_argument("--poisson", action="store_true",
+                    help="also time V_mu (isdf_poisson) on the step's Theta")
     ap.add_argument("--weight-study", default="",
                     help="comma-separated weight functions (ssm,psm,sm,scm,sqm) to compare by fit residuals")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -326,6 +358,8 @@ def main():
                      "frac": round(achieved / PEAK["fp64"], 4), "traffic": traffic,
                      "flops_per_launch": flops, "ms_per_launch": round(solve_ms, 3)},
     }
+    if args.poisson:
+        out["poisson"] = poisson_leg(st, wl, args.steps)
     if args.mixed:
         theta64 = st.theta.clone()  # (the last block when streamed)
         del st

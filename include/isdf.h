@@ -284,6 +284,25 @@ int isdf_cluster_residual(const isdf_grid* grid /* host */, isdf_dtype dt,
                           const int32_t* labels, const int32_t* idx, int32_t n_mu, double* out,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------ potentials */
+/*
+ * V_mu(r) = int zeta_mu(r') / |r - r'| dr' for every column zeta_mu of Theta
+ * (eq. V_mu: the Poisson-like solves ISDF reduces to N_mu), on the periodic
+ * grid: V-hat(G) = 4 pi zeta-hat(G) / |G|^2 with G = 2 pi m / (n_a h_a) per
+ * axis and the G = 0 term dropped (neutralising background).
+ *   theta  [N_r][ld_theta], N_r = n0 n1 n2 in the grid's point order; real
+ *          (is_complex = 0, as isdf_fit returns for Psi = Phi) or
+ *          interleaved complex; double (ISDF_C128) or float (ISDF_C64)
+ *   V      [N_r][ld_v], same type and kind; may not alias theta
+ * Every axis must be <= 256 points with prime factors in {2, 3, 5, 7}
+ * (else ISDF_E_UNSUPPORTED).  FP64 arithmetic; workspace:
+ * isdf_poisson_workspace bytes (0 for an unsupported grid).
+ */
+size_t isdf_poisson_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t is_complex);
+int isdf_poisson(const isdf_grid* grid /* host */, isdf_dtype dt, const void* theta, int64_t ld_theta,
+                 int32_t n_mu, int32_t is_complex, void* V, int64_t ld_v, void* ws, size_t ws_bytes,
+                 void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* isdf_version(void);
 const char* isdf_strerror(int status);

@@ -282,3 +282,30 @@ def cluster_residual(phi: torch.Tensor, psi: torch.Tensor | None, labels: torch.
     if r[1] != 0:
         raise ValueError(f"{int(r[1])} rows have a label outside [0, n_mu) or an invalid interpolation point")
     return r[0]
+
+
+def poisson(theta: torch.Tensor, grid, h=(1.0, 1.0, 1.0)) -> torch.Tensor:
+    """V_mu = int zeta_mu(r') / |r - r'| dr' for every column of Theta
+    (isdf_poisson): theta [N_r][N_mu] real or complex, double or single, on
+    the periodic grid `grid` (n or (n0, n1, n2)) with spacings h (Bohr)."""
+    lib = L.load()
+    if theta.dim() != 2 or theta.stride(1) != 1 or not theta.is_cuda:
+        raise TypeError("theta must be a 2-D CUDA tensor with unit column stride")
+    kinds = {torch.float64: (L.C128, 0), torch.float32: (L.C64, 0), torch.complex128: (L.C128, 1),
+             torch.complex64: (L.C64, 1)}
+    if theta.dtype not in kinds:
+        raise TypeError("theta must be float64, float32, complex128 or complex64")
+    dt, cplx = kinds[theta.dtype]
+    n_r, n_mu = theta.shape
+    g = L.make_grid(grid, h)
+    if g.n[0] * g.n[1] * g.n[2] != n_r:
+        raise ValueError("grid does not match the rows of theta")
+    V = torch.empty(n_r, n_mu, dtype=theta.dtype, device=theta.device)
+    wsb = lib.isdf_poisson_workspace(C.byref(g), n_mu, cplx)
+    if wsb == 0:
+        raise ISDFError(L.E_UNSUPPORTED, "isdf_poisson_workspace")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=theta.device)
+    code = lib.isdf_poisson(C.byref(g), dt, theta.data_ptr(), theta.stride(0), n_mu, cplx, V.data_ptr(), n_mu,
+                            ws.data_ptr(), ws.numel(), _stream_handle())
+    _check(code, "isdf_poisson")
+    return V

@@ -134,3 +134,18 @@ def test_residual_entry_points_reject_bad_arguments():
                                  1 << 30, None) == L.E_ARG
     assert lib.isdf_fit_residual(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, 0, FAKE, 512, FAKE, FAKE, FAKE,
                                  16, None) == L.E_WORKSPACE
+
+
+def test_poisson_rejects_bad_arguments():
+    lib = L.load()
+    g = L.make_grid(8)
+    assert lib.isdf_poisson_workspace(C.byref(g), 10, 0) > 0
+    bad = L.make_grid((8, 11, 8))  # prime factor 11
+    assert lib.isdf_poisson_workspace(C.byref(bad), 10, 0) == 0
+    assert lib.isdf_poisson(C.byref(bad), L.C128, FAKE, 10, 10, 0, FAKE, 10, FAKE, 1 << 30, None) == L.E_UNSUPPORTED
+    big = L.make_grid((8, 8, 288))  # axis above 256 points
+    assert lib.isdf_poisson(C.byref(big), L.C128, FAKE, 10, 10, 0, FAKE, 10, FAKE, 1 << 30, None) == L.E_UNSUPPORTED
+    assert lib.isdf_poisson(C.byref(g), L.C128, FAKE, 9, 10, 0, FAKE, 10, FAKE, 1 << 30, None) == L.E_ARG
+    assert lib.isdf_poisson(C.byref(g), L.C128, FAKE, 10, 10, 0, FAKE, 10, FAKE, 8, None) == L.E_WORKSPACE
+    g0 = L.make_grid(8, (1.0, 0.0, 1.0))
+    assert lib.isdf_poisson(C.byref(g0), L.C128, FAKE, 10, 10, 0, FAKE, 10, FAKE, 1 << 30, None) == L.E_ARG
