@@ -50,7 +50,7 @@ __all__ = [
     "WEIGHT_KINDS", "weight", "grid_points", "metric_scale", "sqdist",
     "assign", "update", "snap", "kmeans", "gather", "gram_blocks", "hadamard",
     "fit", "fit_theta", "fit_backward", "fit_residual", "cluster_residual",
-    "cc_condition", "explicit_z", "reciprocal_sq", "poisson",
+    "cc_condition", "explicit_z", "reciprocal_sq", "poisson", "exchange", "exchange_direct",
 ]
 
 # --------------------------------------------------------------------------
@@ -344,6 +344,31 @@ def poisson(theta: np.ndarray, n, h=(1.0, 1.0, 1.0)) -> np.ndarray:
     zh = np.fft.fftn(z, axes=(0, 1, 2))
     v = np.fft.ifftn(zh * kern[..., None], axes=(0, 1, 2)).reshape(theta.shape)
     return v.real.copy() if np.isrealobj(theta) else v
+
+
+def exchange(phi: np.ndarray, psi: np.ndarray, idx: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """ISDF-compressed exchange of eq. v2: (V_X psi_j)(r) ~
+    -sum_mu V'_mu(r) sum_i phi_i(r) phi_i*(r_mu) psi_j(r_mu), i.e.
+    -((V' . A) Psi_mu) with A = Phi Phi_mu^H.  Eq. v2 expands the pair
+    density phi_i* psi_j, the complex conjugate of Sec. 2.1's
+    z_ij = phi_i psi_j*, whose interpolation vectors are conj(Theta); the
+    potentials of those are conj(V) for V = poisson(Theta) (the Poisson
+    operator is real), so V' = conj(v).  Returns [N_r][N_psi] complex."""
+    idx = np.asarray(idx)
+    A = phi @ phi[idx].conj().T
+    return -((np.conj(v) * A) @ psi[idx])
+
+
+def exchange_direct(phi: np.ndarray, psi: np.ndarray, n, h=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """Exact exchange of eq. vx / eq. v on the grid, for checking eq. v2:
+    (V_X psi_j)(r) = -sum_i phi_i(r) V[phi_i* psi_j](r), with V[.] the
+    periodic Poisson potential of poisson().  Tiny inputs only (N_phi N_psi
+    potentials)."""
+    out = np.zeros((phi.shape[0], psi.shape[1]), dtype=np.complex128)
+    for j in range(psi.shape[1]):
+        pair = phi.conj() * psi[:, j:j + 1]             # phi_i*(r') psi_j(r'), one column per i
+        out[:, j] = -np.sum(phi * poisson(pair, n, h), axis=1)
+    return out
 
 
 def explicit_z(phi: np.ndarray, psi: np.ndarray) -> np.ndarray:

@@ -519,3 +519,36 @@ def test_poisson_background_real_and_linear():
     vxy = oracle.poisson(x + 1j * y, n, h)
     assert np.max(np.abs(vxy.real - vx)) <= 1e-12 * np.max(np.abs(vx))
     assert np.max(np.abs(vxy - vx - 1j * oracle.poisson(y, n, h))) <= 1e-12 * np.max(np.abs(vxy))
+
+
+def test_exchange_is_exact_when_every_point_interpolates():
+    """N_mu = N_r (every grid point an interpolation point): ISDF is exact, so
+    eq. v2 with V = poisson(Theta) equals the exact exchange of eq. v computed
+    from explicit pair densities (complex Phi != Psi, anisotropic grid)."""
+    rng = np.random.default_rng(71)
+    n, h = (3, 2, 4), (0.9, 1.2, 0.7)
+    nr = 24
+    phi = rng.standard_normal((nr, 5)) + 1j * rng.standard_normal((nr, 5))
+    psi = rng.standard_normal((nr, 6)) + 1j * rng.standard_normal((nr, 6))
+    idx = np.arange(nr)
+    theta = oracle.fit_theta(phi, psi, idx)
+    v = oracle.poisson(theta, n, h)
+    got = oracle.exchange(phi, psi, idx, v)
+    ref = oracle.exchange_direct(phi, psi, n, h)
+    assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_exchange_real_orbitals_and_linearity():
+    """Real orbitals give a real exchange; the map is linear in Psi."""
+    rng = np.random.default_rng(72)
+    n = (4, 3, 2)
+    nr = 24
+    phi = rng.standard_normal((nr, 4))
+    idx = rng.choice(nr, 10, replace=False)
+    theta = oracle.fit_theta(phi, phi, idx).real
+    v = oracle.poisson(theta, n)
+    x = oracle.exchange(phi, phi, idx, v)
+    assert np.max(np.abs(x.imag)) <= 1e-14 * np.max(np.abs(x.real))
+    psi2 = rng.standard_normal((nr, 3)) + 1j * rng.standard_normal((nr, 3))
+    y = oracle.exchange(phi, psi2, idx, v)
+    assert np.allclose(oracle.exchange(phi, 2j * psi2, idx, v), 2j * y, rtol=0, atol=1e-13 * np.abs(y).max())
