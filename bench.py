@@ -110,7 +110,7 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int) -> dict:
     return out
 
 
-def poisson_leg(st, wl, steps) -> dict:
+def poisson_leg(st, wl, steps, exchange=False) -> dict:
     """V_mu for every column of the step's Theta (isdf_poisson), HIP-event
     timed; algorithmic bytes: Theta read once and V written once, plus the
     four intermediate passes over the complex work array (real Theta packs
@@ -134,10 +134,27 @@ def poisson_leg(st, wl, steps) -> dict:
     work = th.shape[0] * cols * 16
     io = th.numel() * th.element_size()
     nbytes = 2 * io + 8 * work  # 5 passes: Theta in, V out, 4 x (W in + W out) in between
+    out = {"ms": round(ms, 3), "bound": "hbm", "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
+           "frac": round(nbytes / ms / 1e6 / HBM_PEAK, 4), "columns": th.shape[1],
+           "note": "includes the per-call workspace allocation by the Python wrapper"}
+    if exchange:
+        # exchange of eq. v2 on the step's own orbitals: Gram 8 N_r N_mu N_phi
+        # plus the product with Psi_mu 8 N_r N_mu N_psi, FP64
+        api.exchange(st.phi, st.psi, st.idx, v)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            w = api.exchange(st.phi, st.psi, st.idx, v)
+        b.record()
+        torch.cuda.synchronize()
+        ms_x = a.elapsed_time(b) / steps
+        flops = 8.0 * th.shape[0] * wl.n_mu * (wl.n_phi + wl.n_psi)
+        out["exchange"] = {"ms": round(ms_x, 3), "bound": "mfma", "flops": flops,
+                           "TFLOP/s": round(flops / ms_x / 1e9, 2), "peak": MFMA_PEAK["fp64"],
+                           "frac": round(flops / ms_x / 1e9 / MFMA_PEAK["fp64"], 4)}
+        del w
     del v
-    return {"ms": round(ms, 3), "bound": "hbm", "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
-            "frac": round(nbytes / ms / 1e6 / HBM_PEAK, 4), "columns": th.shape[1],
-            "note": "includes the per-call workspace allocation by the Python wrapper"}
+    return out
 
 
 def weight_study(phi, psi, wl, d, kinds) -> dict:
@@ -240,6 +257,8 @@ def main():
                     help="time the step as replays of one captured HIP graph (phases still from eager steps)")
     ap.add_argument("--poisson", action="store_true",
                     help="also time V_mu (isdf_poisson) on the step's Theta")
+    ap.add_argument("--exchange", action="store_true",
+                    help="with --poisson: also time the ISDF-compressed exchange (isdf_exchange)")
     ap.add_argument("--weight-study", default="",
                     help="comma-separated weight functions (ssm,psm,sm,scm,sqm) to compare by fit residuals")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -359,7 +378,7 @@ def main():
                      "flops_per_launch": flops, "ms_per_launch": round(solve_ms, 3)},
     }
     if args.poisson:
-        out["poisson"] = poisson_leg(st, wl, args.steps)
+        out["poisson"] = poisson_leg(st, wl, args.steps, args.exchange)
     if args.mixed:
         theta64 = st.theta.clone()  # (the last block when streamed)
         del st

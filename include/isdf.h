@@ -303,6 +303,29 @@ int isdf_poisson(const isdf_grid* grid /* host */, isdf_dtype dt, const void* th
                  int32_t n_mu, int32_t is_complex, void* V, int64_t ld_v, void* ws, size_t ws_bytes,
                  void* stream);
 
+/*
+ * ISDF-compressed exchange operator (eq. v2): for every psi_j,
+ *   W(r, j) = (V_X psi_j)(r) ~ - sum_mu conj(V_mu(r)) A(r, mu) psi_j(r_mu),
+ *   A = Phi Phi_mu^H,
+ * with V the potentials isdf_poisson returns for the fit's Theta (eq. v2
+ * expands the pair density phi_i* psi_j, the conjugate of the one the fit
+ * interpolates, whose interpolation vectors are conj(Theta)).
+ *   phi [N_r][ld_phi] (the occupied orbitals), psi [N_r][ld_psi] (the
+ *   orbitals the operator acts on), idx [n_mu]: as for isdf_fit
+ *   V   [N_r][ld_v], real (v_complex = 0) or interleaved complex, same
+ *       storage type as the orbitals
+ *   W   [N_r][ld_w] interleaved complex, storage type of the orbitals
+ * FP64 arithmetic, rblock grid rows per step; workspace:
+ * isdf_exchange_workspace bytes.
+ */
+size_t isdf_exchange_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                               int64_t rblock);
+int isdf_exchange(const isdf_grid* grid /* host */, isdf_dtype dt,
+                  const void* phi, int64_t ld_phi, int32_t n_phi,
+                  const void* psi, int64_t ld_psi, int32_t n_psi,
+                  const int32_t* idx, int32_t n_mu, const void* V, int64_t ld_v, int32_t v_complex,
+                  void* W, int64_t ld_w, int64_t rblock, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* isdf_version(void);
 const char* isdf_strerror(int status);

@@ -64,6 +64,9 @@ SIGNATURES = {
                                     _P, _P, _SZ, _P]),
     "isdf_poisson_workspace": (_SZ, [_G, _I32, _I32]),
     "isdf_poisson": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _I32, _P, _I64, _P, _SZ, _P]),
+    "isdf_exchange_workspace": (_SZ, [_G, _I32, _I32, _I32, _I64]),
+    "isdf_exchange": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, _P, _I64, _I32, _P, _I64,
+                                _I64, _P, _SZ, _P]),
     "isdf_cluster_residual_workspace": (_SZ, []),
     "isdf_cluster_residual": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _P, _I32, _P, _P, _SZ,
                                         _P]),

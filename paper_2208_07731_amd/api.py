@@ -309,3 +309,28 @@ def poisson(theta: torch.Tensor, grid, h=(1.0, 1.0, 1.0)) -> torch.Tensor:
                             ws.data_ptr(), ws.numel(), _stream_handle())
     _check(code, "isdf_poisson")
     return V
+
+
+def exchange(phi: torch.Tensor, psi: torch.Tensor, idx: torch.Tensor, V: torch.Tensor, *,
+             rblock: int | None = None, grid=None) -> torch.Tensor:
+    """ISDF-compressed exchange W = V_X psi (isdf_exchange, eq. v2) from the
+    potentials V of the fit's Theta (as returned by `poisson`)."""
+    lib = L.load()
+    psi, dt, pp, lp, npf, ps, lps, nps, _ = _fit_common(phi, psi, idx)
+    n_r, n_mu = phi.shape[0], idx.numel()
+    if V.shape != (n_r, n_mu) or V.stride(1) != 1 or V.device != phi.device:
+        raise TypeError("V must be (N_r, n_mu) with unit column stride on the orbitals' device")
+    want_real = torch.float64 if dt == L.C128 else torch.float32
+    want_cplx = torch.complex128 if dt == L.C128 else torch.complex64
+    if V.dtype not in (want_real, want_cplx):
+        raise TypeError(f"V must be {want_real} or {want_cplx}")
+    g = _grid(grid, n_r, (1.0, 1.0, 1.0), geometry=False)
+    rblock = min(n_r, 1 << 16) if rblock is None else rblock
+    W = torch.empty(n_r, nps, dtype=want_cplx, device=phi.device)
+    wsb = lib.isdf_exchange_workspace(C.byref(g), n_mu, npf, nps, rblock)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=phi.device)
+    code = lib.isdf_exchange(C.byref(g), dt, pp, lp, npf, ps, lps, nps, idx.data_ptr(), n_mu, V.data_ptr(),
+                             V.stride(0), int(V.is_complex()), W.data_ptr(), nps, rblock, ws.data_ptr(), ws.numel(),
+                             _stream_handle())
+    _check(code, "isdf_exchange")
+    return W

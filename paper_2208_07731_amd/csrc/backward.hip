@@ -48,26 +48,6 @@ __global__ void adj_hadamard(const double* __restrict__ S, double* __restrict__ 
   }
 }
 
-// F[n][k] (n = 2 i + c', k = 2 nu + c): real form of right-multiplication by
-// Phi_mu, (x + iy)(a + ib) = (xa - yb) + i(xb + ya) with Phi_mu[nu][i] = a + ib.
-template <class TS, class T>
-__global__ void pack_adj_rhs(const TS* __restrict__ phi, int64_t ld, int n, const int32_t* __restrict__ idx,
-                             int n_mu, int64_t nr, T* __restrict__ F) {
-  const int64_t total = (int64_t)2 * n * 2 * n_mu;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int row = (int)(e / (2 * n_mu)), k = (int)(e % (2 * n_mu));
-    const int i = row >> 1, cp = row & 1, nu = k >> 1, c = k & 1;
-    int64_t p = idx[nu];
-    if (p < 0 || p >= nr) p = 0;
-    const double2 z = Cplx<TS>::load(phi + 2 * (p * ld + i));
-    double v;
-    if (cp == 0) v = c == 0 ? z.x : -z.y;
-    else v = c == 0 ? z.y : z.x;
-    F[e] = (T)v;
-  }
-}
-
 // Real rows of Phi at the interpolation points: X[mu][k] = Phi_real[idx[mu]][k].
 template <class TS, class T>
 __global__ void gather_rows(const TS* __restrict__ phi, int64_t ld, int n, const int32_t* __restrict__ idx,
