@@ -48,7 +48,7 @@ typedef enum {
   ISDF_E_ARG = -1,          /* invalid argument (host check, nothing enqueued) */
   ISDF_E_WORKSPACE = -2,    /* ws_bytes below the *_workspace query */
   ISDF_E_HIP = -3,          /* a HIP runtime call failed while enqueueing */
-  ISDF_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  ISDF_E_UNSUPPORTED = -4,  /* valid request outside what the library implements (e.g. a grid axis isdf_poisson cannot transform) */
   ISDF_E_NOT_PD = 1,        /* device: C C^H not positive definite (see info->pivot) */
   ISDF_E_NONFINITE = 2,     /* device: NaN or Inf in the orbitals / weight */
   ISDF_W_EMPTY_CLUSTER = 3, /* device: a cluster lost all members (idx = -1) */
