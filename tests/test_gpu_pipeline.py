@@ -88,3 +88,26 @@ def test_graph_replay_matches_eager(water8_step):
         x = torch.randn(1000, device="cuda").sum()
         torch.cuda.synchronize()
         assert torch.isfinite(x)
+
+
+def test_step_general_psi_matches_api():
+    """Psi != Phi (strided views of one array), complex Theta, streamed
+    blocks: the whole step equals the one-shot calls bit for bit."""
+    rng = np.random.default_rng(91)
+    n = (6, 7, 8)
+    nr = 336
+    big = rng.standard_normal((nr, 14)) + 1j * rng.standard_normal((nr, 14))
+    t = dev(big)
+    phi, psi = t[:, :5], t[:, 5:14]
+    g = dev(rng.uniform(0.5, 1.5, nr))
+    c0 = oracle.grid_points(n)[rng.choice(nr, 24, replace=False)]
+    st = ISDFStep(phi, psi, 24, c0, 8, g=g, grid=n, block_rows=100)
+    st.enqueue()
+    st.check()
+    km = isdf.kmeans(phi, psi, 24, c0, 8, grid=n)
+    assert torch.equal(st.idx, km.idx)
+    theta, minv, _ = isdf.fit(phi, psi, km.idx, grid=n)
+    assert torch.equal(st.theta, theta)
+    dphi, dpsi, loss, _ = isdf.fit_backward(phi, psi, km.idx, minv, g=g, grid=n, rblock=st.rblock)
+    assert torch.equal(st.dphi, dphi) and torch.equal(st.dpsi, dpsi)
+    assert st.loss.item() == loss.item()
