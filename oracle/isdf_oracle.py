@@ -51,6 +51,7 @@ __all__ = [
     "assign", "update", "snap", "kmeans", "gather", "gram_blocks", "hadamard",
     "fit", "fit_theta", "fit_backward", "fit_residual", "cluster_residual",
     "cc_condition", "explicit_z", "reciprocal_sq", "poisson", "exchange", "exchange_direct",
+    "qrcp", "qrcp_greedy_excess", "qrcp_sampled_check",
 ]
 
 # --------------------------------------------------------------------------
@@ -375,6 +376,99 @@ def explicit_z(phi: np.ndarray, psi: np.ndarray) -> np.ndarray:
     """Z (N_r x N_phi N_psi), z_(i,j)(r) = phi_i(r) conj(psi_j(r)) (Sec. 2.1).
     Tiny inputs only: memory is O(N_r N_phi N_psi)."""
     return (phi[:, :, None] * psi.conj()[:, None, :]).reshape(phi.shape[0], -1)
+
+
+# --------------------------------------------------------------------------
+# interpolation points by QR with column pivoting (Sec. 2.1, eq. QRCP; Table 1)
+# --------------------------------------------------------------------------
+def _suffix_sq(w: np.ndarray) -> np.ndarray:
+    """s[k, j] = sum_{i >= k} |w[i, j]|^2: the squared norm of column j of a
+    matrix whose rows are coordinates in an orthonormal basis, once the first
+    k basis vectors are projected out."""
+    a = w.real ** 2 + w.imag ** 2
+    return np.cumsum(a[::-1], axis=0)[::-1]
+
+
+def qrcp(phi: np.ndarray, psi: np.ndarray, n_mu: int, rtol: float = 1e-7) -> dict:
+    """Interpolation points from the QR factorisation with column pivoting
+    of Z^T (Sec. 2.1, eq. QRCP): Z^T Pi = Q R with |R_kk| non-increasing; the
+    first n_mu pivot columns of Z^T (grid points) are the interpolation
+    points.  Z is formed explicitly (tiny inputs only) and factored by
+    LAPACK's pivoted Householder QR (geqp3).  The paper's baseline is a
+    randomized QRCP that approximates these pivots from a sketch of Z^T; this
+    is the exact factorisation it approximates.
+
+    Returns dict:
+      idx    [n_mu] int64 grid index of pivot k; -1 from the numerical rank on
+      rdiag  [n_mu] |R_kk| (0 from the rank on)
+      gap    [n_mu] (s_1 - s_2) / s_1 with s_1 >= s_2 the two largest squared
+             residual column norms at step k: the margin of the pivot choice
+      rank   number of k < n_mu with |R_kk| > rtol |R_00|
+    Exact ties follow LAPACK's column order (not necessarily lowest index).
+    """
+    zt = explicit_z(phi, psi).T                     # (N_phi N_psi) x N_r
+    r, piv = sla.qr(zt, mode="r", pivoting=True)
+    m = min(zt.shape)
+    r = r[:m]
+    kmax = min(n_mu, m)
+    s = _suffix_sq(r)
+    rdiag = np.zeros(n_mu)
+    gap = np.zeros(n_mu)
+    idx = np.full(n_mu, -1, dtype=np.int64)
+    d = np.abs(np.diag(r))
+    rank = 0
+    for k in range(kmax):
+        if not d[k] > rtol * d[0]:
+            break
+        rank = k + 1
+        idx[k] = piv[k]
+        rdiag[k] = d[k]
+        rest = s[k, k + 1:]
+        s2 = rest.max() if rest.size else 0.0
+        gap[k] = (s[k, k] - s2) / s[k, k]
+    return dict(idx=idx, rdiag=rdiag, gap=gap, rank=rank)
+
+
+def qrcp_greedy_excess(phi: np.ndarray, psi: np.ndarray, idx) -> np.ndarray:
+    """Brute-force check of the pivot rule behind eq. QRCP for a given pivot
+    order: with Q_k an orthonormal basis of the first k chosen columns of
+    Z^T, pivot k must have the largest norm of (I - Q_k Q_k^H) z over all
+    columns z.  Returns, per step, (max_z s_k(z) - s_k(idx[k])) / s_0(idx[0]),
+    which is >= 0 up to rounding and 0 for a greedy order.  Tiny inputs only.
+    A property test: `idx` may come from any implementation."""
+    idx = np.asarray(idx)
+    zt = explicit_z(phi, psi).T
+    q, _ = np.linalg.qr(zt[:, idx], mode="complete")
+    s = _suffix_sq(q.conj().T @ zt)
+    ex = np.array([s[k].max() - s[k, idx[k]] for k in range(len(idx))])
+    return ex / s[0, idx[0]]
+
+
+def qrcp_sampled_check(phi: np.ndarray, psi: np.ndarray, idx, rdiag, rows) -> dict:
+    """Properties of a pivot sequence that hold at any size, computed
+    without Z from its Gram matrix K = Z Z^H = (Phi Phi^H) .* conj(Psi Psi^H)
+    (whose pivoted Cholesky factor L has |L_kk| = |R_kk| of eq. QRCP):
+      * rdiag[k]^2 equals the k-th squared diagonal of the Cholesky factor of
+        K at the pivots (in pivot order): returns the largest relative error;
+      * greedy rule at the sampled grid rows: the squared residual of every
+        sampled non-pivot row after k steps, K_rr - sum_{j<k} |L_rj|^2, is
+        at most rdiag[k]^2: returns the largest excess relative to rdiag[0]^2.
+    A property test: idx and rdiag may come from any implementation."""
+    idx = np.asarray(idx)
+    rows = np.setdiff1d(np.asarray(rows), idx)
+    kpp = hadamard(*gram_blocks(phi, psi, idx, rows=idx))
+    lp = sla.cholesky(kpp, lower=True)
+    diag2 = np.abs(np.diag(lp)) ** 2
+    rd2 = np.asarray(rdiag, dtype=np.float64) ** 2
+    rel = float(np.max(np.abs(diag2 - rd2) / diag2))
+    krp = hadamard(*gram_blocks(phi, psi, idx, rows=rows))       # K(rows, P)
+    lr = sla.solve_triangular(lp, krp.conj().T, lower=True).conj().T   # L(rows, :) = K(rows, P) L_P^-H
+    krr = ((phi[rows].real ** 2 + phi[rows].imag ** 2).sum(axis=1)
+           * (psi[rows].real ** 2 + psi[rows].imag ** 2).sum(axis=1))
+    a = lr.real ** 2 + lr.imag ** 2
+    before = krr[:, None] - np.concatenate([np.zeros((len(rows), 1)), np.cumsum(a, axis=1)[:, :-1]], axis=1)
+    excess = float(np.max(before - rd2[None, :]) / rd2[0])
+    return dict(rdiag_rel=rel, greedy_excess=excess)
 
 
 # --------------------------------------------------------------------------

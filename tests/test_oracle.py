@@ -552,3 +552,117 @@ def test_exchange_real_orbitals_and_linearity():
     psi2 = rng.standard_normal((nr, 3)) + 1j * rng.standard_normal((nr, 3))
     y = oracle.exchange(phi, psi2, idx, v)
     assert np.allclose(oracle.exchange(phi, 2j * psi2, idx, v), 2j * y, rtol=0, atol=1e-13 * np.abs(y).max())
+
+
+# ------------------------------------------------------ QRCP points (eq. QRCP)
+def _orth(rng, nr, n):
+    return np.linalg.qr(crandn(rng, nr, n))[0]
+
+
+@pytest.mark.parametrize("aliased", [True, False])
+def test_qrcp_is_greedy_by_bruteforce(aliased):
+    """eq. QRCP: every pivot has the largest residual column norm of Z^T after
+    projecting out the earlier pivots (checked with an orthonormal basis of
+    the chosen columns, not with R), and |R_kk| does not increase."""
+    rng = np.random.default_rng(80 + aliased)
+    phi = _orth(rng, 400, 5)
+    psi = phi if aliased else _orth(rng, 400, 4)
+    o = oracle.qrcp(phi, psi, 18)
+    assert o["rank"] == 18
+    ex = oracle.qrcp_greedy_excess(phi, psi, o["idx"])
+    assert ex.max() <= 1e-12 and ex.min() >= -1e-12
+    assert np.all(np.diff(o["rdiag"]) <= 1e-15 * o["rdiag"][0])
+    assert len(set(o["idx"].tolist())) == 18
+    # the Gram/Cholesky property check agrees on a greedy sequence
+    c = oracle.qrcp_sampled_check(phi, psi, o["idx"], o["rdiag"], np.arange(400))
+    assert c["rdiag_rel"] <= 1e-12 and c["greedy_excess"] <= 1e-12
+
+
+def test_qrcp_checks_catch_a_wrong_pivot():
+    """The two property checks fail on planted mistakes: two pivots swapped
+    (brute force), and a pivot replaced by a lower-residual row with a
+    self-consistent R diagonal (Gram check)."""
+    rng = np.random.default_rng(82)
+    phi, psi = _orth(rng, 300, 4), _orth(rng, 300, 5)
+    o = oracle.qrcp(phi, psi, 12)
+    bad = o["idx"].copy()
+    bad[[2, 6]] = bad[[6, 2]]
+    assert oracle.qrcp_greedy_excess(phi, psi, bad).max() > 1e-3
+    bad = o["idx"].copy()
+    bad[4] = np.setdiff1d(np.arange(300), bad)[0]
+    kpp = oracle.hadamard(*oracle.gram_blocks(phi, psi, bad, rows=bad))
+    rd = np.abs(np.diag(sla.cholesky(kpp, lower=True)))
+    assert oracle.qrcp_sampled_check(phi, psi, bad, rd, np.arange(300))["greedy_excess"] > 1e-3
+
+
+def test_qrcp_gap_by_explicit_projection():
+    """gap[k] = (s_1 - s_2) / s_1 for the two largest squared norms of the
+    columns of (I - P_k) Z^T, P_k the orthogonal projector on the first k
+    pivot columns (formed from a least-squares solve, not from R)."""
+    rng = np.random.default_rng(83)
+    phi, psi = _orth(rng, 120, 3), _orth(rng, 120, 3)
+    o = oracle.qrcp(phi, psi, 6)
+    zt = oracle.explicit_z(phi, psi).T
+    for k in range(6):
+        if k == 0:
+            res = zt
+        else:
+            b = zt[:, o["idx"][:k]]
+            coef = np.linalg.lstsq(b, zt, rcond=None)[0]
+            res = zt - b @ coef
+        s = np.sort((np.abs(res) ** 2).sum(axis=0))[::-1]
+        assert abs(s[0] - o["rdiag"][k] ** 2) <= 1e-12 * o["rdiag"][0] ** 2
+        assert abs((s[0] - s[1]) / s[0] - o["gap"][k]) <= 1e-9
+
+
+@pytest.mark.parametrize("n_phi,n_psi,real,rank", [(2, 2, False, 4), (2, 3, False, 6), (3, 3, True, 6)])
+def test_qrcp_rank_closed_form_and_exact_fit(n_phi, n_psi, real, rank):
+    """Z has N_phi N_psi columns of rank N_phi N_psi for generic complex
+    orbitals, and N(N+1)/2 for real Phi = Psi (phi_i phi_j = phi_j phi_i).
+    QRCP stops at that rank (eq. QRCP: R11 non-singular, the rest zero), and
+    the fit at those points reproduces Z exactly (eq. decomposition)."""
+    rng = np.random.default_rng(84 + n_psi)
+    nr = 200
+    if real:
+        phi = np.linalg.qr(rng.standard_normal((nr, n_phi)))[0].astype(np.complex128)
+        psi = phi
+    else:
+        phi = _orth(rng, nr, n_phi)
+        psi = phi if n_psi == n_phi else _orth(rng, nr, n_psi)
+    o = oracle.qrcp(phi, psi, rank + 3, rtol=1e-8)
+    assert o["rank"] == rank
+    assert np.all(o["idx"][rank:] == -1) and np.all(o["rdiag"][rank:] == 0)
+    idx = o["idx"][:rank]
+    theta = oracle.fit_theta(phi, psi, idx)
+    z = oracle.explicit_z(phi, psi)
+    assert np.linalg.norm(theta @ z[idx] - z) <= 1e-10 * np.linalg.norm(z)
+
+
+def test_qrcp_single_orbital_pair():
+    """N_phi = N_psi = 1: Z^T is one row, so the first pivot is the grid point
+    of largest |phi||psi| and |R_00| is that value; the rank is 1."""
+    rng = np.random.default_rng(86)
+    phi = crandn(rng, 97, 1)
+    psi = crandn(rng, 97, 1)
+    o = oracle.qrcp(phi, psi, 3)
+    m = np.abs(phi[:, 0]) * np.abs(psi[:, 0])
+    assert o["rank"] == 1 and o["idx"][0] == np.argmax(m)
+    assert abs(o["rdiag"][0] - m.max()) <= 1e-14 * m.max()
+
+
+def test_qrcp_permutation_and_gauge_equivariant():
+    """Relabelling grid points relabels the pivots; a unitary mixing of the
+    orbitals (Phi U, Psi V) leaves Z Z^H and hence the pivots and |R_kk|
+    unchanged (Sec. 2.1: Z only enters through its row space)."""
+    rng = np.random.default_rng(87)
+    nr = 350
+    phi, psi = _orth(rng, nr, 4), _orth(rng, nr, 5)
+    o = oracle.qrcp(phi, psi, 15)
+    assert o["gap"].min() > 1e-8
+    perm = rng.permutation(nr)
+    op = oracle.qrcp(phi[perm], psi[perm], 15)
+    inv = np.argsort(perm)
+    assert np.array_equal(op["idx"], inv[o["idx"]])
+    og = oracle.qrcp(phi @ haar_unitary(rng, 4), psi @ haar_unitary(rng, 5), 15)
+    assert np.array_equal(og["idx"], o["idx"])
+    assert np.allclose(og["rdiag"], o["rdiag"], rtol=1e-12, atol=0)
