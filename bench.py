@@ -157,6 +157,51 @@ def poisson_leg(st, wl, steps, exchange=False) -> dict:
     return out
 
 
+def qrcp_leg(phi, psi, wl, km_idx, km_ms, steps) -> dict:
+    """Interpolation points by QRCP of Z^T (isdf_qrcp, eq. QRCP), the paper's
+    baseline for K-means: HIP-event time of the whole selection, its
+    algorithmic HBM bytes (each of the N_mu - 1 column steps reads the
+    orbitals and the first k columns of L and writes column k and the
+    residual diagonal), and the FP64 fit's least-squares residual at the QRCP
+    points beside the K-means points'."""
+    import math
+
+    import torch
+
+    from paper_2208_07731_amd import api
+
+    psi_arg = None if wl.aliased else psi
+    api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        r = api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    esz = phi.element_size()
+    cw = 8 if wl.aliased else 16
+    orb = wl.n_r * (wl.n_phi + (0 if wl.aliased else wl.n_psi)) * esz
+    nk = wl.n_mu - 1
+    lread = wl.n_r * cw * nk * (nk - 1) / 2.0
+    nbytes = nk * (orb + wl.n_r * (cw + 16)) + lread
+    out = {"ms": round(ms, 2), "bound": "hbm", "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
+           "frac": round(nbytes / ms / 1e6 / HBM_PEAK, 4), "rank": r.info["rank"],
+           "near_ties": r.info["near_ties"], "r_last_over_r00": float(r.rdiag[-1] / r.rdiag[0]),
+           "kmeans_ms": km_ms, "qrcp_over_kmeans_time": round(ms / km_ms, 1) if km_ms else None}
+    for name, idx in (("qrcp", r.idx), ("kmeans", km_idx)):
+        idx = idx[idx >= 0].contiguous()
+        _, minv, info = api.fit(phi, psi_arg, idx, nrows=0)
+        res, zz = api.fit_residual(phi, psi_arg, idx, minv, rblock=wl.rblock or None)
+        out[f"{name}_ls_rel_residual"] = math.sqrt(max(res, 0.0) / zz)
+        out[f"{name}_cc_pivot_ratio"] = info["pivot_max"] / info["pivot_min"] if info["pivot_min"] > 0 else None
+        del minv
+    torch.cuda.empty_cache()
+    log(f"[bench] qrcp: {out}")
+    return out
+
+
 def weight_study(phi, psi, wl, d, kinds) -> dict:
     """K-means with each weight function (eq. weight function for PSM, eq.
     weight function 2 for alpha = 1..4), then the FP64 fit: the relative
@@ -259,6 +304,8 @@ def main():
                     help="also time V_mu (isdf_poisson) on the step's Theta")
     ap.add_argument("--exchange", action="store_true",
                     help="with --poisson: also time the ISDF-compressed exchange (isdf_exchange)")
+    ap.add_argument("--qrcp", action="store_true",
+                    help="also select the points by QRCP of Z^T (isdf_qrcp) and compare with K-means")
     ap.add_argument("--weight-study", default="",
                     help="comma-separated weight functions (ssm,psm,sm,scm,sqm) to compare by fit residuals")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -379,6 +426,8 @@ def main():
     }
     if args.poisson:
         out["poisson"] = poisson_leg(st, wl, args.steps, args.exchange)
+    if args.qrcp:
+        out["qrcp"] = qrcp_leg(phi, psi, wl, st.idx.clone(), phases["kmeans"], 1)
     if args.mixed:
         theta64 = st.theta.clone()  # (the last block when streamed)
         del st

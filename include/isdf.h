@@ -326,6 +326,57 @@ int isdf_exchange(const isdf_grid* grid /* host */, isdf_dtype dt,
                   const int32_t* idx, int32_t n_mu, const void* V, int64_t ld_v, int32_t v_complex,
                   void* W, int64_t ld_w, int64_t rblock, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------- QRCP interpolation points */
+/* Written by the device at the end of isdf_qrcp. */
+typedef struct {
+  int32_t status;    /* ISDF_OK or ISDF_E_NONFINITE */
+  int32_t rank;      /* pivots accepted: n_mu unless the residual fell to rtol |R_00| first */
+  int32_t near_ties; /* accepted steps whose gap <= near_tie_rel */
+  int32_t reserved;
+  double r00;        /* |R_00| = max_r |Z(r)| */
+} isdf_qrcp_info;
+
+/* Bytes of workspace isdf_qrcp needs (0 for invalid sizes): about
+ * (n_mu - 1) N_r doubles, twice that for Psi != Phi.  Host-only. */
+size_t isdf_qrcp_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t aliased);
+
+/*
+ * Interpolation points by QR factorisation with column pivoting of Z^T
+ * (Sec. 2.1, eq. QRCP; the baseline the paper compares K-means against):
+ *   Z^T Pi = Q R, |R_00| >= |R_11| >= ...,  idx[k] = grid point of pivot k.
+ * Z is not formed: the pivots are those of the pivoted Cholesky
+ * factorisation of Z Z^H = (Phi Phi^H) .* conj(Psi Psi^H), whose diagonal
+ * after k steps holds the squared residual norms of Z^T's columns.  Step k
+ * takes the largest residual (lowest grid index on exact ties).  The paper's
+ * randomized variant approximates these exact pivots.
+ * Arguments:
+ *   phi, psi      orbitals (see conventions); psi == phi selects the aliased
+ *                 (real Gram) path
+ *   n_mu          pivots wanted, 1 <= n_mu <= N_r
+ *   rtol          stop once the largest residual |R_kk| <= rtol |R_00|; the
+ *                 Gram formulation resolves |R_kk| down to about 1e-7 |R_00|
+ *                 in FP64, so rtol should not be smaller
+ *   near_tie_rel  steps whose gap <= near_tie_rel are counted in info
+ *   idx           [n_mu] int32 out: pivot grid indices in order; -1 from rank on
+ *   rdiag         [n_mu] FP64 out: |R_kk|; 0 from rank on
+ *   gap           [n_mu] FP64 out (NULL: not returned): (s1 - s2) / s1 for the
+ *                 two largest squared residuals s1 >= s2 at step k, the
+ *                 margin of the pivot choice
+ *   info          device struct, written at the end
+ * FP64 arithmetic throughout; C64 orbitals are widened on load.  Cost:
+ * n_mu passes over the orbitals and over the growing factor L (N_r x k),
+ * O(n_mu N_r (N_phi + N_psi) + n_mu^2 N_r) (Table 1: QRCP is O(N_mu^2 N_r)).
+ * ISDF_E_UNSUPPORTED if Phi(p) and Psi(p) do not fit the step kernel's LDS
+ * (N_phi + N_psi above about 3000).  Deterministic: equal inputs give
+ * bitwise equal outputs.
+ */
+int isdf_qrcp(const isdf_grid* grid /* host */, isdf_dtype dt,
+              const void* phi, int64_t ld_phi, int32_t n_phi,
+              const void* psi, int64_t ld_psi, int32_t n_psi,
+              int32_t n_mu, double rtol, double near_tie_rel,
+              int32_t* idx, double* rdiag, double* gap, isdf_qrcp_info* info,
+              void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* isdf_version(void);
 const char* isdf_strerror(int status);

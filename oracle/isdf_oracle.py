@@ -449,7 +449,8 @@ def qrcp_sampled_check(phi: np.ndarray, psi: np.ndarray, idx, rdiag, rows) -> di
     without Z from its Gram matrix K = Z Z^H = (Phi Phi^H) .* conj(Psi Psi^H)
     (whose pivoted Cholesky factor L has |L_kk| = |R_kk| of eq. QRCP):
       * rdiag[k]^2 equals the k-th squared diagonal of the Cholesky factor of
-        K at the pivots (in pivot order): returns the largest relative error;
+        K at the pivots (in pivot order): returns the largest difference
+        relative to the first (rdiag_rel);
       * greedy rule at the sampled grid rows: the squared residual of every
         sampled non-pivot row after k steps, K_rr - sum_{j<k} |L_rj|^2, is
         at most rdiag[k]^2: returns the largest excess relative to rdiag[0]^2.
@@ -460,7 +461,7 @@ def qrcp_sampled_check(phi: np.ndarray, psi: np.ndarray, idx, rdiag, rows) -> di
     lp = sla.cholesky(kpp, lower=True)
     diag2 = np.abs(np.diag(lp)) ** 2
     rd2 = np.asarray(rdiag, dtype=np.float64) ** 2
-    rel = float(np.max(np.abs(diag2 - rd2) / diag2))
+    rel = float(np.max(np.abs(diag2 - rd2)) / diag2[0])
     krp = hadamard(*gram_blocks(phi, psi, idx, rows=rows))       # K(rows, P)
     lr = sla.solve_triangular(lp, krp.conj().T, lower=True).conj().T   # L(rows, :) = K(rows, P) L_P^-H
     krr = ((phi[rows].real ** 2 + phi[rows].imag ** 2).sum(axis=1)

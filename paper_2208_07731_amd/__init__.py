@@ -4,8 +4,8 @@ interpolation vectors and their adjoint, after arXiv:2208.07731.
 The computation lives in libisdf.so (hand-written HIP kernels behind the C ABI
 of include/isdf.h); this package is the Python binding.
 """
-from .api import (ISDFError, KMeansResult, cluster_residual, exchange, fit, fit_backward,  # noqa: F401
-                  fit_residual, kmeans, poisson)
+from .api import (ISDFError, KMeansResult, QRCPResult, cluster_residual, exchange, fit,  # noqa: F401
+                  fit_backward, fit_residual, kmeans, poisson, qrcp)
 from .autograd import ISDFFit, ISDFLoss  # noqa: F401
 
 __all__ = ["kmeans", "fit", "fit_backward", "ISDFFit", "ISDFLoss", "ISDFError", "KMeansResult"]

@@ -32,6 +32,11 @@ class KmeansInfo(C.Structure):
                 ("near_ties", C.c_int32), ("changed", C.c_int32), ("objective", C.c_double)]
 
 
+class QrcpInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("rank", C.c_int32), ("near_ties", C.c_int32),
+                ("reserved", C.c_int32), ("r00", C.c_double)]
+
+
 class FitInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("pivot", C.c_int32), ("bad_idx", C.c_int32),
                 ("reserved", C.c_int32), ("pivot_min", C.c_double), ("pivot_max", C.c_double),
@@ -67,6 +72,9 @@ SIGNATURES = {
     "isdf_exchange_workspace": (_SZ, [_G, _I32, _I32, _I32, _I64]),
     "isdf_exchange": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, _P, _I64, _I32, _P, _I64,
                                 _I64, _P, _SZ, _P]),
+    "isdf_qrcp_workspace": (_SZ, [_G, _I32, _I32]),
+    "isdf_qrcp": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _SZ,
+                            _P]),
     "isdf_cluster_residual_workspace": (_SZ, []),
     "isdf_cluster_residual": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _P, _I32, _P, _P, _SZ,
                                         _P]),

@@ -128,6 +128,45 @@ def kmeans(phi: torch.Tensor | None, psi: torch.Tensor | None, n_mu: int, c0, ma
     return KMeansResult(idx, cent, labels, wout, obj, d)
 
 
+@dataclasses.dataclass
+class QRCPResult:
+    idx: torch.Tensor    # int32 [n_mu], -1 from the rank on
+    rdiag: torch.Tensor  # float64 [n_mu], |R_kk|
+    gap: torch.Tensor    # float64 [n_mu], decision margin of each pivot
+    info: dict
+
+
+def qrcp(phi: torch.Tensor, psi: torch.Tensor | None, n_mu: int, *, rtol: float = 1e-7,
+         near_tie_rel: float = 1e-9, grid=None) -> QRCPResult:
+    """Interpolation points by QR with column pivoting of Z^T (isdf_qrcp,
+    eq. QRCP), Z never formed.  psi None or psi is phi: the aliased path."""
+    lib = L.load()
+    if psi is None:
+        psi = phi
+    dt, pp, lp, npf = _orbital(phi, "phi")
+    dt2, ps, lps, nps = _orbital(psi, "psi")
+    if dt2 != dt or psi.shape[0] != phi.shape[0] or psi.device != phi.device:
+        raise TypeError("phi and psi must share dtype, row count and device")
+    n_r = phi.shape[0]
+    g = _grid(grid, n_r, (1.0, 1.0, 1.0), geometry=False)
+    dev = phi.device
+    idx = torch.empty(n_mu, dtype=torch.int32, device=dev)
+    rdiag = torch.empty(n_mu, dtype=torch.float64, device=dev)
+    gap = torch.empty(n_mu, dtype=torch.float64, device=dev)
+    info = torch.zeros(C.sizeof(L.QrcpInfo), dtype=torch.uint8, device=dev)
+    wsb = lib.isdf_qrcp_workspace(C.byref(g), n_mu, int(_same(phi, psi)))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    code = lib.isdf_qrcp(C.byref(g), dt, pp, lp, npf, ps, lps, nps, n_mu, rtol, near_tie_rel, idx.data_ptr(),
+                         rdiag.data_ptr(), gap.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                         _stream_handle())
+    _check(code, "isdf_qrcp")
+    torch.cuda.current_stream().synchronize()
+    inf = _read_struct(info, L.QrcpInfo)
+    if inf.status != L.OK:
+        raise ISDFError(inf.status, "isdf_qrcp")
+    return QRCPResult(idx, rdiag, gap, {f: getattr(inf, f) for f, _ in L.QrcpInfo._fields_})
+
+
 def _prec(prec: str) -> int:
     if prec not in L.PRECS:
         raise ValueError(f"prec must be one of {list(L.PRECS)}")

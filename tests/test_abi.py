@@ -149,3 +149,34 @@ def test_poisson_rejects_bad_arguments():
     assert lib.isdf_poisson(C.byref(g), L.C128, FAKE, 10, 10, 0, FAKE, 10, FAKE, 8, None) == L.E_WORKSPACE
     g0 = L.make_grid(8, (1.0, 0.0, 1.0))
     assert lib.isdf_poisson(C.byref(g0), L.C128, FAKE, 10, 10, 0, FAKE, 10, FAKE, 1 << 30, None) == L.E_ARG
+
+
+def test_qrcp_rejects_bad_arguments():
+    lib = L.load()
+    g = L.make_grid(8)
+    wa = lib.isdf_qrcp_workspace(C.byref(g), 10, 1)
+    wc = lib.isdf_qrcp_workspace(C.byref(g), 10, 0)
+    assert 0 < wa < wc and wa >= 9 * 512 * 8 and wc >= 9 * 512 * 16
+    assert lib.isdf_qrcp_workspace(C.byref(g), 0, 1) == 0
+
+    def call(**over):
+        kw = dict(dt=L.C128, phi=FAKE, ld=4, n=4, psi=FAKE, ldp=4, np_=4, n_mu=10, rtol=1e-7, ntr=1e-9,
+                  idx=FAKE, rd=FAKE, gap=None, info=FAKE, ws=FAKE, wsb=1 << 30)
+        kw.update(over)
+        return lib.isdf_qrcp(C.byref(g), kw["dt"], kw["phi"], kw["ld"], kw["n"], kw["psi"], kw["ldp"], kw["np_"],
+                             kw["n_mu"], kw["rtol"], kw["ntr"], kw["idx"], kw["rd"], kw["gap"], kw["info"], kw["ws"],
+                             kw["wsb"], None)
+
+    assert call(n_mu=0) == L.E_ARG
+    assert call(n_mu=513) == L.E_ARG
+    assert call(idx=None) == L.E_ARG
+    assert call(rd=None) == L.E_ARG
+    assert call(info=None) == L.E_ARG
+    assert call(ld=3) == L.E_ARG
+    assert call(dt=5) == L.E_ARG
+    assert call(rtol=1.0) == L.E_ARG
+    assert call(rtol=-1.0) == L.E_ARG
+    assert call(ntr=float("nan")) == L.E_ARG
+    assert call(wsb=wa - 1) == L.E_WORKSPACE
+    assert call(psi=FAKE + 64, wsb=wc - 1) == L.E_WORKSPACE  # Psi != Phi needs the complex workspace
+    assert call(n=3000, ld=3000, psi=FAKE + 64, np_=3000, ldp=3000) == L.E_UNSUPPORTED
