@@ -30,6 +30,9 @@ the design notes):
 * Distances: D = ((s0*dx*dx) + (s1*dy*dy)) + (s2*dz*dz) in grid units with
   s_a = (h_a / min h)^2 (s = 1 on cubic grids, where integer-valued
   coordinates make first-iteration ties exact).
+* QRCP interpolation points (Sec. 2.1, eq. QRCP): the exact pivoted QR
+  factorisation of Z^T, which the paper's randomized QRCP approximates; the
+  numerical rank ends at |R_kk| <= rtol |R_00|.
 * The adjoint is not in the paper; it is derived by reverse-mode
   differentiation of the fit with the interpolation points held fixed, in
   PyTorch's complex-gradient convention dL/dRe + i dL/dIm.
