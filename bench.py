@@ -69,7 +69,7 @@ MFMA_PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0, "fp16x3": 2500.0}  #
 ISSUED = {"fp64": 1, "fp32": 1, "bf16x6": 6, "fp16x3": 3}  # MFMA products per algorithmic product
 
 
-def phase_rates(wl, prec: str, phases: dict, rounds: int) -> dict:
+def phase_rates(wl, prec: str, phases: dict, rounds: int, saved_gram: bool = False) -> dict:
     """Algorithmic work of each phase, its rate and its fraction of the
     roofline that bounds it.
 
@@ -80,9 +80,10 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int) -> dict:
     zc     : 8 N_r N_mu (N_phi [+ N_psi]); split precisions issue 6x / 3x
              as many 16-bit MFMA products, against the 16-bit peak.
     solve  : 2 N_r n1^2 (FP64).
-    adjoint: Gram recompute 8 N_r N_mu N, orbital products Abar F and Abar^T X
-             16 N_r N_mu N, and the fused-loss FP64 products: H = G^T g G over
-             the lower half (N_r n1^2) and S = G M^-2 (2 N_r n1^2).
+    adjoint: Gram recompute 8 N_r N_mu N (not when the forward saved the
+             Gram blocks), orbital products Abar F and Abar^T X 16 N_r N_mu N,
+             and the fused-loss FP64 products: H = G^T g G over the lower half
+             (N_r n1^2) and S = G M^-2 (2 N_r n1^2).
     """
     n_e = wl.n_phi + (0 if wl.aliased else wl.n_psi)
     esize = 16
@@ -98,7 +99,7 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int) -> dict:
         "factor": (8.0 * wl.n_mu ** 2 * n_e + float(n1) ** 3, "fp64", 1),
         "zc": (8.0 * wl.n_r * wl.n_mu * n_e, prec, ISSUED[prec]),
         "solve": (2.0 * wl.n_r * n1 * n1, "fp64", 1),
-        "adjoint": (24.0 * wl.n_r * wl.n_mu * n_e + 3.0 * wl.n_r * n1 * n1, "fp64", 1),
+        "adjoint": ((16.0 if saved_gram else 24.0) * wl.n_r * wl.n_mu * n_e + 3.0 * wl.n_r * n1 * n1, "fp64", 1),
     }
     for name, (flops, pk, issued) in work.items():
         ms = phases[name]
@@ -414,10 +415,11 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.n}^3 grid (N_r={wl.n_r}), N_e={wl.n_phi}, N_mu={wl.n_mu}, "
                                f"{'Phi=Psi' if wl.aliased else 'Phi!=Psi'}, K-means {wl.kmeans_iters} rounds, "
                                f"fit + fused-loss adjoint"
+                               + (" (Gram blocks kept from the forward)" if st.save_gram else "")
                                + (f", Z C^H and Theta streamed in blocks of {block_rows} rows" if block_rows else ""),
                    "gram_prec": args.prec},
         "phases_ms": phases,
-        "phases": phase_rates(wl, args.prec, phases, info["kmeans"]["iters"]),
+        "phases": phase_rates(wl, args.prec, phases, info["kmeans"]["iters"], st.save_gram),
         "kmeans": {"rounds": info["kmeans"]["iters"], "converged": info["kmeans"]["converged"]},
         "roofline": {"bound": "mfma", "kernel": "FP64 GEMM Theta = (Z C^H)(C C^H)^-1",
                      "achieved": round(achieved, 2), "peak": PEAK["fp64"], "unit": "TFLOP/s",

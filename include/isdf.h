@@ -205,6 +205,20 @@ int isdf_zc(const isdf_grid* grid /* host */, isdf_dtype dt,
             void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * isdf_zc_ab: isdf_zc that also keeps the Gram blocks of the same rows,
+ *   A = Phi Phi_mu^H and (Psi != Phi only) B = Psi Psi_mu^H,
+ * as [nrows][2 n_mu] interleaved complex FP64 (ld 2 n_mu), for
+ * isdf_fit_backward_gram.  Same workspace as isdf_zc.  B is unused (may be
+ * NULL) in the aliased case.
+ */
+int isdf_zc_ab(const isdf_grid* grid /* host */, isdf_dtype dt,
+               const void* phi, int64_t ld_phi, int32_t n_phi,
+               const void* psi, int64_t ld_psi, int32_t n_psi,
+               const int32_t* idx, int32_t n_mu, isdf_prec prec,
+               int64_t row0, int64_t nrows, double* G, int64_t ldg, double* A, double* B,
+               void* ws, size_t ws_bytes, void* stream);
+
+/*
  * isdf_apply_minv: Theta = G (C C^H)^-1 for `nrows` rows (the solve of
  * eq. theta), minv as left by isdf_fit with ISDF_FIT_FACTOR, G as written by
  * isdf_zc.  theta: [nrows][ld_theta], real (aliased) or interleaved complex,
@@ -243,6 +257,30 @@ int isdf_fit_backward(const isdf_grid* grid /* host */, isdf_dtype dt,
                       void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi,
                       double* loss, int64_t rblock,
                       isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * isdf_fit_backward from the forward's Gram blocks: the same adjoint, with
+ * the Gram product of every r-block replaced by the rows of G, A and B that
+ * isdf_zc_ab wrote for the whole grid (G [N_r][n'] with n' = n_mu aliased
+ * or 2 n_mu, A and B [N_r][2 n_mu]; B unused when Psi = Phi).  A, B and G
+ * are consumed: the adjoint overwrites them in place.  The r-block loop and
+ * every reduction order are those of isdf_fit_backward with the same rblock,
+ * so the gradients and the loss are bitwise equal to it; the workspace
+ * (isdf_fit_backward_gram_workspace) holds no r-block copies of G, A, B.
+ * Trades N_r (n' + 2 n_mu [+ 2 n_mu]) doubles kept from the forward for one
+ * Gram product per call.
+ */
+size_t isdf_fit_backward_gram_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi,
+                                        int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock);
+int isdf_fit_backward_gram(const isdf_grid* grid /* host */, isdf_dtype dt,
+                           const void* phi, int64_t ld_phi, int32_t n_phi,
+                           const void* psi, int64_t ld_psi, int32_t n_psi,
+                           const int32_t* idx, int32_t n_mu, isdf_prec prec,
+                           const double* minv,
+                           const void* theta_bar, int64_t ld_tbar, const double* g,
+                           void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi,
+                           double* loss, int64_t rblock, double* G, double* A, double* B,
+                           isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------- residuals */
 /*

@@ -61,9 +61,14 @@ SIGNATURES = {
     "isdf_zc_workspace": (_SZ, [_I32, _I32, _I32, _I32, C.c_int, _I64]),
     "isdf_zc": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _I64, _I64, _P, _I64,
                           _P, _SZ, _P]),
+    "isdf_zc_ab": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _I64, _I64, _P, _I64,
+                             _P, _P, _P, _SZ, _P]),
     "isdf_apply_minv": (C.c_int, [_I32, _I32, _P, _P, _I64, _I64, C.c_int, _P, _I64, _P]),
     "isdf_fit_backward": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _P,
                                     _P, _I64, _P, _P, _I64, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
+    "isdf_fit_backward_gram_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32, C.c_int, _I64]),
+    "isdf_fit_backward_gram": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _P,
+                                         _P, _I64, _P, _P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
     "isdf_fit_residual_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32, C.c_int, _I64]),
     "isdf_fit_residual": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _P, _I64, _P,
                                     _P, _P, _SZ, _P]),

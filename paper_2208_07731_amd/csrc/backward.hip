@@ -7,7 +7,10 @@
 //   Abar = Gbar .* B,  Bbar = conj(Gbar) .* A,
 //   dPhi = Abar Phi_mu,  dPhi[idx] += Abar^H Phi,  (same for Psi with Bbar).
 //
-// G, A, B are recomputed one r-block at a time and never stored whole.
+// G, A, B are recomputed one r-block at a time and never stored whole, or,
+// for callers that kept them from the forward (isdf_zc_ab), read from there
+// and overwritten in place; the r-block loop and every reduction order are
+// the same either way, so both give bitwise equal gradients.
 // General upstream Thetabar: per block Theta = G M^-1 and S = Thetabar M^-1
 // (FP64 GEMMs), the split-K partials of Theta^T S, Abar / Bbar in place.
 // Fused loss L = sum_r g_r sum_mu |Theta_r,mu|^2 (Thetabar = 2 g Theta):
@@ -321,7 +324,7 @@ struct BwdPlan {
 };
 
 static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, int n_psi, bool aliased,
-                        isdf_prec prec, int64_t rblock, int slots) {
+                        isdf_prec prec, int64_t rblock, int slots, bool saved = false) {
   const size_t tsize = tsize_of(prec);
   // largest split factors over the block sizes that occur (both losses)
   int sh = 1, sq = 1;
@@ -350,10 +353,12 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
     P.Fpsi = c.take<char>((size_t)2 * n_psi * 2 * n_mu * tsize);
     P.Xpsi = c.take<char>((size_t)n_mu * 2 * n_psi * tsize);
   }
-  P.G = c.take<double>((size_t)rblock * n1);
+  if (!saved) {  // else the caller's saved Gram blocks stand in for G, A, B
+    P.G = c.take<double>((size_t)rblock * n1);
+    P.A = c.take<double>((size_t)rblock * 2 * n_mu);
+    if (!aliased) P.B = c.take<double>((size_t)rblock * 2 * n_mu);
+  }
   P.Th = c.take<double>((size_t)rblock * n1);
-  P.A = c.take<double>((size_t)rblock * 2 * n_mu);
-  if (!aliased) P.B = c.take<double>((size_t)rblock * 2 * n_mu);
   P.P = c.take<double>((size_t)n1 * n1);
   P.W2 = c.take<double>((size_t)n1 * n1);
   P.Ppart = c.take<double>((size_t)sh * n1 * n1);
@@ -438,7 +443,8 @@ template <int PREC, class TS, class TT>
 static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                    bool aliased, const int32_t* idx, int n_mu, const double* minv, const TT* tbar, int64_t ld_tbar,
                    const double* g, TS* dphi, int64_t ld_dphi, TS* dpsi, int64_t ld_dpsi, double* loss,
-                   int64_t rblock, isdf_fit_info* info, const BwdPlan& P, hipStream_t s) {
+                   int64_t rblock, double* Gs, double* As, double* Bs, isdf_fit_info* info, const BwdPlan& P,
+                   hipStream_t s) {
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   const int n1 = aliased ? n_mu : 2 * n_mu;
   const int* ab = &P.st->abort;
@@ -474,13 +480,17 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   }
   if (!tbar && !dgemm<KC, KC, double>(n1, n1, n1, minv, n1, minv, n1, P.W2, n1, 1.0, 0.0, 0, ab, s))
     return ISDF_E_HIP;  // (C C^H)^-2
-  double* Abar = aliased ? P.A : P.B;  // after the Hadamard step
-  double* Bbar = P.A;
   for (int64_t r = 0; r < nr; r += rblock) {
     const int rows = (int)(nr - r < rblock ? nr - r : rblock);
-    // Gram blocks of the r-block: A (and B) kept, G for Theta
-    if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr, r,
-                        rows, P.G, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, &P.sw, P.A, aliased ? nullptr : P.B))
+    // Gram blocks of the r-block: A (and B) kept, G for Theta; saved by the
+    // forward (isdf_zc_ab) or recomputed here
+    double* Gb = Gs ? Gs + r * n1 : P.G;
+    double* Ab = As ? As + r * 2 * n_mu : P.A;
+    double* Bb = aliased ? nullptr : (Bs ? Bs + r * 2 * n_mu : P.B);
+    double* Abar = aliased ? Ab : Bb;  // after the Hadamard step
+    double* Bbar = Ab;
+    if (!Gs && !gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr,
+                               r, rows, Gb, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, &P.sw, Ab, Bb))
       return ISDF_E_HIP;
     const BwdSplits sp_phi = bwd_splits(rows, n1, n_mu, n_phi, !tbar, P.slots);
     const BwdSplits sp_psi = bwd_splits(rows, n1, n_mu, n_psi, !tbar, P.slots);
@@ -488,13 +498,13 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       // H += G^T diag(g) G (lower tiles, split-K, fixed-order reduction)
       const int sp = sp_phi.h;
       const int64_t pn = (int64_t)n1 * n1;
-      if (!tgemm<double, XC, XC>(n1, n1, rows, P.G, n1, P.G, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
+      if (!tgemm<double, XC, XC>(n1, n1, rows, Gb, n1, Gb, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
         return ISDF_E_HIP;
       hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, r > 0 ? 1 : 0,
                          ab);
       // S = 2 g . (G (C C^H)^-2): Abar / Bbar in place and the loss, in the epilogue
-      EpiSAdj epi{P.G, n1, P.A, P.B, 2 * (int64_t)n_mu, g + r, rows, n1, aliased ? 1 : 0, P.lpart};
-      Operand<double> a{P.G, n1, nullptr, nullptr}, b{P.W2, n1, nullptr, nullptr};
+      EpiSAdj epi{Gb, n1, Ab, Bb, 2 * (int64_t)n_mu, g + r, rows, n1, aliased ? 1 : 0, P.lpart};
+      Operand<double> a{Gb, n1, nullptr, nullptr}, b{P.W2, n1, nullptr, nullptr};
       if (!launch_gemm<double, 128, 128, 16, 2, 2, double, KC, double, KC, 1>(rows, n1, n1, a, b, a, b, 0, epi, 0, ab,
                                                                              s))
         return ISDF_E_HIP;
@@ -503,18 +513,18 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       if (!launch_ok()) return ISDF_E_HIP;
     } else {
       // Theta = G M^-1, S = Thetabar M^-1 (over G), P += Theta^T S, Abar / Bbar in place
-      if (!dgemm<KC, KC, double>(rows, n1, n1, P.G, n1, minv, n1, P.Th, n1, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
+      if (!dgemm<KC, KC, double>(rows, n1, n1, Gb, n1, minv, n1, P.Th, n1, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
       const int64_t ldt = aliased ? ld_tbar : 2 * ld_tbar;
-      if (!dgemm<KC, KC, double, TT>(rows, n1, n1, tbar + r * ldt, ldt, minv, n1, P.G, n1, 1.0, 0.0, 0, ab, s))
+      if (!dgemm<KC, KC, double, TT>(rows, n1, n1, tbar + r * ldt, ldt, minv, n1, Gb, n1, 1.0, 0.0, 0, ab, s))
         return ISDF_E_HIP;
       const int sp = sp_phi.h;
       const int64_t pn = (int64_t)n1 * n1;
-      if (!tgemm<double, XC, XC>(n1, n1, rows, P.Th, n1, P.G, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn))
+      if (!tgemm<double, XC, XC>(n1, n1, rows, P.Th, n1, Gb, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn))
         return ISDF_E_HIP;
       hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, r > 0 ? 1 : 0,
                          ab);
-      hipLaunchKernelGGL(adj_hadamard, dim3(blocks_for((int64_t)rows * n_mu)), dim3(256), 0, s, (const double*)P.G,
-                         P.A, P.B, (int64_t)rows, n_mu, aliased ? 1 : 0);
+      hipLaunchKernelGGL(adj_hadamard, dim3(blocks_for((int64_t)rows * n_mu)), dim3(256), 0, s, (const double*)Gb,
+                         Ab, Bb, (int64_t)rows, n_mu, aliased ? 1 : 0);
       if (!launch_ok()) return ISDF_E_HIP;
     }
     if (Prec<PREC>::SPLIT == SPLIT_FP16X3) {  // binary16 scales of Abar, Phi, Bbar, Psi
@@ -558,27 +568,22 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   return ISDF_OK;
 }
 
-}  // namespace
-}  // namespace isdf
-
-using namespace isdf;
-
-extern "C" size_t isdf_fit_backward_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
-                                              int32_t aliased, isdf_prec prec, int64_t rblock) {
+static size_t bwd_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased,
+                            isdf_prec prec, int64_t rblock, bool saved) {
   if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
   for (int a = 0; a < 3; ++a)
     if (grid->n[a] <= 0) return 0;
   const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   if (rblock > nr) rblock = nr;
-  return plan_bwd(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, prec, rblock, device_slots()).bytes;
+  return plan_bwd(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, prec, rblock, device_slots(), saved).bytes;
 }
 
-extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
-                                 int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx,
-                                 int32_t n_mu, isdf_prec prec, const double* minv, const void* theta_bar,
-                                 int64_t ld_tbar, const double* g, void* dphi, int64_t ld_dphi, void* dpsi,
-                                 int64_t ld_dpsi, double* loss, int64_t rblock, isdf_fit_info* info, void* ws,
-                                 size_t ws_bytes, void* stream) {
+static int bwd_dispatch(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+                        const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
+                        isdf_prec prec, const double* minv, const void* theta_bar, int64_t ld_tbar, const double* g,
+                        void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi, double* loss, int64_t rblock,
+                        double* Gs, double* As, double* Bs, bool saved, isdf_fit_info* info, void* ws,
+                        size_t ws_bytes, void* stream) {
   int64_t nr = 0;
   if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
   if (!minv || !info || !dphi || !dpsi || rblock <= 0) return ISDF_E_ARG;
@@ -588,13 +593,15 @@ extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const voi
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
   if (!aliased && dphi == dpsi) return ISDF_E_ARG;
+  if (saved && (!Gs || !As || (!aliased && !Bs))) return ISDF_E_ARG;
+  if (!saved) Gs = As = Bs = nullptr;
   if (rblock > nr) rblock = nr;
-  BwdPlan P = plan_bwd(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, prec, rblock, device_slots());
+  BwdPlan P = plan_bwd(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, prec, rblock, device_slots(), saved);
   if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
 #define ISDF_BWD_ARGS(TS)                                                                                        \
   nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, minv, (const TS*)theta_bar, \
-      ld_tbar, g, (TS*)dphi, ld_dphi, (TS*)dpsi, ld_dpsi, loss, rblock, info, P, s
+      ld_tbar, g, (TS*)dphi, ld_dphi, (TS*)dpsi, ld_dpsi, loss, rblock, Gs, As, Bs, info, P, s
   if (dt == ISDF_C128) {
     switch (prec) {
       case ISDF_P_FP64: return bwd_run<ISDF_P_FP64, double, double>(ISDF_BWD_ARGS(double));
@@ -609,4 +616,41 @@ extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const voi
     default: return bwd_run<ISDF_P_FP16X3, float, float>(ISDF_BWD_ARGS(float));
   }
 #undef ISDF_BWD_ARGS
+}
+
+}  // namespace
+}  // namespace isdf
+
+using namespace isdf;
+
+extern "C" size_t isdf_fit_backward_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                                              int32_t aliased, isdf_prec prec, int64_t rblock) {
+  return bwd_workspace(grid, n_mu, n_phi, n_psi, aliased, prec, rblock, false);
+}
+
+extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+                                 int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx,
+                                 int32_t n_mu, isdf_prec prec, const double* minv, const void* theta_bar,
+                                 int64_t ld_tbar, const double* g, void* dphi, int64_t ld_dphi, void* dpsi,
+                                 int64_t ld_dpsi, double* loss, int64_t rblock, isdf_fit_info* info, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  return bwd_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, minv, theta_bar, ld_tbar, g,
+                      dphi, ld_dphi, dpsi, ld_dpsi, loss, rblock, nullptr, nullptr, nullptr, false, info, ws, ws_bytes,
+                      stream);
+}
+
+extern "C" size_t isdf_fit_backward_gram_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi,
+                                                   int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock) {
+  return bwd_workspace(grid, n_mu, n_phi, n_psi, aliased, prec, rblock, true);
+}
+
+extern "C" int isdf_fit_backward_gram(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+                                      int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
+                                      const int32_t* idx, int32_t n_mu, isdf_prec prec, const double* minv,
+                                      const void* theta_bar, int64_t ld_tbar, const double* g, void* dphi,
+                                      int64_t ld_dphi, void* dpsi, int64_t ld_dpsi, double* loss, int64_t rblock,
+                                      double* G, double* A, double* B, isdf_fit_info* info, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  return bwd_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, minv, theta_bar, ld_tbar, g,
+                      dphi, ld_dphi, dpsi, ld_dpsi, loss, rblock, G, A, B, true, info, ws, ws_bytes, stream);
 }

@@ -311,7 +311,7 @@ extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, 
 template <int PREC, class TS>
 static int zc_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                   bool aliased, const int32_t* idx, int n_mu, int64_t row0, int64_t nrows, double* G, int64_t ldg,
-                  const ZcPlan& P, hipStream_t s) {
+                  double* A, double* B, const ZcPlan& P, hipStream_t s) {
   typedef typename Prec<PREC>::E T;
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   T* Ephi = (T*)P.Ephi;
@@ -323,26 +323,29 @@ static int zc_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS
   if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
     return ISDF_E_HIP;
   if (nrows > 0 && !gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr,
-                                   nr, row0, (int)nrows, G, ldg, aliased ? G_REAL : G_CPLX, P.ab, s, P.sc, &P.sw))
+                                   nr, row0, (int)nrows, G, ldg, aliased ? G_REAL : G_CPLX, P.ab, s, P.sc, &P.sw,
+                                   A, aliased ? nullptr : B))
     return ISDF_E_HIP;
   return ISDF_OK;
 }
 
-extern "C" int isdf_zc(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+static int zc_dispatch(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
                        const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
-                       isdf_prec prec, int64_t row0, int64_t nrows, double* G, int64_t ldg, void* ws,
-                       size_t ws_bytes, void* stream) {
+                       isdf_prec prec, int64_t row0, int64_t nrows, double* G, int64_t ldg, double* A, double* B,
+                       bool want_ab, void* ws, size_t ws_bytes, void* stream) {
   int64_t nr = 0;
   if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
   if (row0 < 0 || nrows < 0 || row0 + nrows > nr || nrows > INT32_MAX || (nrows > 0 && !G)) return ISDF_E_ARG;
   if (ldg < (aliased ? n_mu : 2 * (int64_t)n_mu)) return ISDF_E_ARG;
+  if (want_ab && nrows > 0 && (!A || (!aliased && !B))) return ISDF_E_ARG;
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
   ZcPlan P = plan_zc(ws, ws_bytes, n_mu, n_phi, n_psi, aliased, prec, nrows);
   if (!ws || P.bytes > ws_bytes) return ISDF_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
+  if (!want_ab) A = B = nullptr;
 #define ISDF_ZC_ARGS(TS) \
-  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, row0, nrows, G, ldg, P, s
+  nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, row0, nrows, G, ldg, A, B, P, s
   if (dt == ISDF_C128) {
     switch (prec) {
       case ISDF_P_FP64: return zc_run<ISDF_P_FP64, double>(ISDF_ZC_ARGS(double));
@@ -357,6 +360,22 @@ extern "C" int isdf_zc(const isdf_grid* grid, isdf_dtype dt, const void* phi, in
     default: return zc_run<ISDF_P_FP16X3, float>(ISDF_ZC_ARGS(float));
   }
 #undef ISDF_ZC_ARGS
+}
+
+extern "C" int isdf_zc(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+                       const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
+                       isdf_prec prec, int64_t row0, int64_t nrows, double* G, int64_t ldg, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return zc_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, row0, nrows, G, ldg, nullptr,
+                     nullptr, false, ws, ws_bytes, stream);
+}
+
+extern "C" int isdf_zc_ab(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+                          const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
+                          isdf_prec prec, int64_t row0, int64_t nrows, double* G, int64_t ldg, double* A, double* B,
+                          void* ws, size_t ws_bytes, void* stream) {
+  return zc_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, row0, nrows, G, ldg, A, B,
+                     true, ws, ws_bytes, stream);
 }
 
 extern "C" int isdf_apply_minv(int32_t n_mu, int32_t aliased, const double* minv, const double* G, int64_t ldg,

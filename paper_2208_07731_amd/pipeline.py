@@ -8,6 +8,11 @@ With block_rows < N_r the forward runs Z C^H and Theta block by block
 (block_rows rows at a time); keep_theta=False then keeps only the current
 block of Theta (the streamed form for grids whose Theta does not fit).
 
+When the forward runs as one block, it also keeps the Gram blocks A = Phi
+Phi_mu^H (and B = Psi Psi_mu^H) beside Z C^H (isdf_zc_ab), and the adjoint
+takes them instead of recomputing its Gram products (isdf_fit_backward_gram,
+bitwise the same gradients); save_gram=False recomputes them.
+
 Nothing is allocated and nothing synchronises inside enqueue(): every
 output, workspace and info struct is created in the constructor, and the
 calls go straight to the C ABI on the current stream.  This is the form a
@@ -28,7 +33,7 @@ class ISDFStep:
     def __init__(self, phi: torch.Tensor, psi: torch.Tensor | None, n_mu: int, c0, max_iter: int, *,
                  g: torch.Tensor | None = None, prec: str = "fp64", grid=None, h=(1.0, 1.0, 1.0),
                  rblock: int | None = None, backward: bool = True, near_tie_rel: float = 1e-6,
-                 block_rows: int | None = None, keep_theta: bool = True):
+                 block_rows: int | None = None, keep_theta: bool = True, save_gram: bool | None = None):
         self.lib = L.load()
         psi = phi if psi is None else psi
         self.phi, self.psi = phi, psi
@@ -74,6 +79,15 @@ class ISDFStep:
         cplx_t = torch.complex128 if self.dt == L.C128 else torch.complex64
         self.theta = torch.empty(n_r if self.keep_theta else self.block_rows, n_mu,
                                  dtype=real_t if self.aliased else cplx_t, device=dev)
+        if save_gram is None:
+            save_gram = backward and len(self.blocks) == 1
+        if save_gram and (not backward or len(self.blocks) != 1):
+            raise ValueError("save_gram needs the adjoint and a single forward block")
+        self.save_gram = save_gram
+        self.A = self.B = None
+        if save_gram:
+            self.A = torch.empty(n_r, 2 * n_mu, dtype=f64, device=dev)
+            self.B = None if self.aliased else torch.empty(n_r, 2 * n_mu, dtype=f64, device=dev)
         if backward:
             if g is None:
                 raise ValueError("the adjoint needs the loss field g")
@@ -82,9 +96,13 @@ class ISDFStep:
             self.dpsi = self.dphi if self.aliased else torch.empty(n_r, self.nps, dtype=psi.dtype, device=dev)
             self.loss = torch.zeros((), dtype=f64, device=dev)
             self.bwd_info = torch.zeros(C.sizeof(L.FitInfo), dtype=u8, device=dev)
-            self.bwd_ws = torch.empty(self.lib.isdf_fit_backward_workspace(
-                C.byref(self.grid), n_mu, self.npf, self.nps, int(self.aliased), self.prec, self.rblock),
-                dtype=u8, device=dev)
+            wsq = self.lib.isdf_fit_backward_gram_workspace if save_gram else self.lib.isdf_fit_backward_workspace
+            self.bwd_ws = torch.empty(wsq(C.byref(self.grid), n_mu, self.npf, self.nps, int(self.aliased), self.prec,
+                                          self.rblock), dtype=u8, device=dev)
+
+    @staticmethod
+    def _ptr(t):
+        return None if t is None else t.data_ptr()
 
     def _call(self, code, where):
         if code != L.OK:
@@ -131,9 +149,15 @@ class ISDFStep:
             be = block_events[b] if block_events else None
             if be:
                 be[0].record()
-            self._call(lib.isdf_zc(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
-                                   self.idx.data_ptr(), self.n_mu, self.prec, r0, nrows, self.G.data_ptr(), self.n1,
-                                   self.zc_ws.data_ptr(), self.zc_ws.numel(), s), "isdf_zc")
+            if self.save_gram:
+                self._call(lib.isdf_zc_ab(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
+                                          self.idx.data_ptr(), self.n_mu, self.prec, r0, nrows, self.G.data_ptr(),
+                                          self.n1, self.A.data_ptr(), self._ptr(self.B), self.zc_ws.data_ptr(),
+                                          self.zc_ws.numel(), s), "isdf_zc_ab")
+            else:
+                self._call(lib.isdf_zc(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
+                                       self.idx.data_ptr(), self.n_mu, self.prec, r0, nrows, self.G.data_ptr(),
+                                       self.n1, self.zc_ws.data_ptr(), self.zc_ws.numel(), s), "isdf_zc")
             if be:
                 be[1].record()
             if b == 0:
@@ -144,7 +168,14 @@ class ISDFStep:
             if be:
                 be[2].record()
         mark(3)
-        if self.backward:
+        if self.backward and self.save_gram:
+            self._call(lib.isdf_fit_backward_gram(
+                gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps, self.idx.data_ptr(), self.n_mu,
+                self.prec, self.minv.data_ptr(), None, 0, self.g.data_ptr(), self.dphi.data_ptr(), self.npf,
+                self.dpsi.data_ptr(), self.nps, self.loss.data_ptr(), self.rblock, self.G.data_ptr(),
+                self.A.data_ptr(), self._ptr(self.B), self.bwd_info.data_ptr(), self.bwd_ws.data_ptr(),
+                self.bwd_ws.numel(), s), "isdf_fit_backward_gram")
+        elif self.backward:
             self._call(lib.isdf_fit_backward(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
                                              self.idx.data_ptr(), self.n_mu, self.prec, self.minv.data_ptr(), None,
                                              0, self.g.data_ptr(), self.dphi.data_ptr(), self.npf,

@@ -180,3 +180,26 @@ def test_qrcp_rejects_bad_arguments():
     assert call(wsb=wa - 1) == L.E_WORKSPACE
     assert call(psi=FAKE + 64, wsb=wc - 1) == L.E_WORKSPACE  # Psi != Phi needs the complex workspace
     assert call(n=3000, ld=3000, psi=FAKE + 64, np_=3000, ldp=3000) == L.E_UNSUPPORTED
+
+
+def test_saved_gram_entry_points_reject_bad_arguments():
+    lib = L.load()
+    g = L.make_grid(8)
+    full = lib.isdf_fit_backward_workspace(C.byref(g), 5, 4, 4, 1, 0, 512)
+    saved = lib.isdf_fit_backward_gram_workspace(C.byref(g), 5, 4, 4, 1, 0, 512)
+    assert 0 < saved < full  # no r-block copies of G and A
+    # isdf_zc_ab: A missing
+    assert lib.isdf_zc_ab(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, 0, 0, 512, FAKE, 5, None, None,
+                          FAKE, 1 << 30, None) == L.E_ARG
+    # Psi != Phi: B missing
+    assert lib.isdf_zc_ab(C.byref(g), L.C128, FAKE, 4, 4, FAKE + 64, 4, 4, FAKE, 5, 0, 0, 512, FAKE, 10, FAKE, None,
+                          FAKE, 1 << 30, None) == L.E_ARG
+
+    def bwd(G=FAKE, A=FAKE, B=None, wsb=1 << 30, psi=FAKE):
+        return lib.isdf_fit_backward_gram(C.byref(g), L.C128, FAKE, 4, 4, psi, 4, 4, FAKE, 5, 0, FAKE, None, 0, FAKE,
+                                          FAKE, 4, FAKE + 4096, 4, None, 512, G, A, B, FAKE, FAKE, wsb, None)
+
+    assert bwd(G=None) == L.E_ARG
+    assert bwd(A=None) == L.E_ARG
+    assert bwd(psi=FAKE + 64) == L.E_ARG  # general case needs B
+    assert bwd(wsb=saved - 1) == L.E_WORKSPACE

@@ -111,3 +111,35 @@ def test_step_general_psi_matches_api():
     dphi, dpsi, loss, _ = isdf.fit_backward(phi, psi, km.idx, minv, g=g, grid=n, rblock=st.rblock)
     assert torch.equal(st.dphi, dphi) and torch.equal(st.dpsi, dpsi)
     assert st.loss.item() == loss.item()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6", "fp16x3"])
+@pytest.mark.parametrize("general", [False, True])
+def test_saved_gram_adjoint_bitwise(prec, general):
+    """The adjoint from the forward's Gram blocks (isdf_zc_ab +
+    isdf_fit_backward_gram) gives the recomputing adjoint's gradients and
+    loss bit for bit, with ragged backward r-blocks (rblock = 100)."""
+    rng = np.random.default_rng(92 + general)
+    n = (6, 7, 8)
+    nr = 336
+    big = rng.standard_normal((nr, 14)) + 1j * rng.standard_normal((nr, 14))
+    t = dev(big)
+    phi = t[:, :5]
+    psi = t[:, 5:14] if general else None
+    g = dev(rng.uniform(0.5, 1.5, nr))
+    c0 = oracle.grid_points(n)[rng.choice(nr, 24, replace=False)]
+    out = []
+    for save in (True, False):
+        st = ISDFStep(phi, psi, 24, c0, 8, g=g, grid=n, prec=prec, rblock=100, save_gram=save)
+        assert st.save_gram == save
+        st.enqueue()
+        st.check()
+        out.append(st)
+    a, b = out
+    assert torch.equal(a.theta, b.theta)
+    assert torch.equal(a.dphi, b.dphi) and torch.equal(a.dpsi, b.dpsi)
+    assert a.loss.item() == b.loss.item()
+    # and again on the same buffers (the saved blocks are rewritten each step)
+    a.enqueue()
+    a.check()
+    assert torch.equal(a.dphi, b.dphi) and a.loss.item() == b.loss.item()
