@@ -102,7 +102,9 @@ struct TileCfg {
 template <class T, int LAYOUT, int X, int BK>
 struct Lds {
   static constexpr int PK = 16 / (int)sizeof(T);  // 16-byte pad per row
-  static constexpr int PX = 16;
+  // XC rows padded by 4 elements: the four lane groups of a read (rows 4
+  // apart) then start 32 (FP64) or 16 (FP32) banks apart
+  static constexpr int PX = 4;
   static constexpr int SIZE = LAYOUT == KC ? X * (BK + PK) : BK * (X + PX);
   __device__ __forceinline__ static int at(int x, int k) {
     return LAYOUT == KC ? x * (BK + PK) + k : k * (X + PX) + x;
@@ -126,7 +128,8 @@ __device__ __forceinline__ void load_pair<float>(const float* p, double& a, doub
 
 // Per-thread prefetch of one BK slice of an operand (X rows x BK), in the
 // compute type.  KC: thread -> (x, run of E consecutive k); XC: thread ->
-// (k, run of E consecutive x).  Interior slices of aligned operands use
+// (k, E / 2 pairs of consecutive x), consecutive threads on consecutive
+// pairs.  Interior slices of aligned operands use
 // unguarded pair loads; edge slices guard every element.
 template <class T, class TS, int LAYOUT, int X, int BK, int THREADS>
 struct Stager {
@@ -163,23 +166,30 @@ struct Stager {
         }
       }
     } else {
-      constexpr int RUNS = X / E;  // threads per k
+      // RUNS threads per k row; pair c of a thread sits 2 RUNS elements to
+      // the right of pair c - 1, so consecutive lanes take consecutive x
+      // pairs and a wave instruction reads whole cache lines
+      constexpr int RUNS = X / E;
       const int64_t k = k0 + tid / RUNS;
-      const int xb = x0 + (tid % RUNS) * E;
+      const int xb = x0 + 2 * (tid % RUNS);
       const TS* base = op.p + k * op.ld + xb;
       const double f = (op.kscale && k < klim) ? op.kscale[k] : 1.0;
       if (interior) {
 #pragma unroll
-        for (int e = 0; e < E; e += 2) {
+        for (int c = 0; c < E / 2; ++c) {
           double a, b;
-          load_pair<TS>(base + e, a, b);
-          v[e] = (T)(a * f);
-          v[e + 1] = (T)(b * f);
+          load_pair<TS>(base + 2 * RUNS * c, a, b);
+          v[2 * c] = (T)(a * f);
+          v[2 * c + 1] = (T)(b * f);
         }
       } else {
         const bool okk = k < klim;
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = (okk && xb + e < xlim) ? (T)(base[e] * f) : (T)0;
+        for (int c = 0; c < E / 2; ++c) {
+          const int x = xb + 2 * RUNS * c;
+          v[2 * c] = (okk && x < xlim) ? (T)(base[2 * RUNS * c] * f) : (T)0;
+          v[2 * c + 1] = (okk && x + 1 < xlim) ? (T)(base[2 * RUNS * c + 1] * f) : (T)0;
+        }
       }
     }
   }
@@ -192,9 +202,12 @@ struct Stager {
       for (int e = 0; e < E; ++e) d[e] = v[e];
     } else {
       constexpr int RUNS = X / E;
-      T* d = s + L::at((tid % RUNS) * E, tid / RUNS);
+      T* d = s + L::at(2 * (tid % RUNS), tid / RUNS);
 #pragma unroll
-      for (int e = 0; e < E; ++e) d[e] = v[e];
+      for (int c = 0; c < E / 2; ++c) {
+        d[2 * RUNS * c] = v[2 * c];
+        d[2 * RUNS * c + 1] = v[2 * c + 1];
+      }
     }
   }
   // Global row of this thread's x (KC), resolved once per tile.
