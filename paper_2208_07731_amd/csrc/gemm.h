@@ -10,8 +10,9 @@
 // array (KC only).  The accumulator tile is handed to an epilogue functor.
 //
 // Tiling: a BM x BN block tile per workgroup of WM x WN wavefronts, BK-deep
-// K steps staged through LDS (k-major, padded), register prefetch of the
-// next K step while the current one feeds the MFMAs.  Each wavefront owns a
+// K steps staged through LDS (double buffered, padded), register prefetch of
+// the K step after next, and a software-pipelined step (fragment reads,
+// stores and the barrier placed between pairs of MFMA sub-steps).  Each wavefront owns a
 // (BM/WM) x (BN/WN) sub-tile made of 16x16 MFMA tiles:
 //   T = double: v_mfma_f64_16x16x4f64, T = float: v_mfma_f32_16x16x4f32.
 // Operand lane layout of both (16x4 A, 4x16 B): lane l holds row/col l%16,
@@ -257,6 +258,129 @@ __device__ __forceinline__ void fold_into(A (&acc)[Cfg::MI][Cfg::NI], FoldAcc<Cf
     }
 }
 
+// Operand values of lane `lane` for sub-steps s0 and s0 + 1 of chunk c:
+// elements (x, 16 c + 4 (lane / 16) + s0 + t), t = 0, 1.
+template <class T, int LAYOUT, int X, int BK>
+__device__ __forceinline__ void read2(const T* s, int x, int c, int s0, int lane, T (&o)[2]) {
+  typedef Lds<T, LAYOUT, X, BK> L;
+  const int k = 16 * c + 4 * (lane >> 4) + s0;
+  if (LAYOUT == KC) {
+    const T* p = s + L::at(x, k);
+    o[0] = p[0];
+    o[1] = p[1];
+  } else {
+    o[0] = s[L::at(x, k)];
+    o[1] = s[L::at(x, k + 1)];
+  }
+}
+
+// Runs the K loop of one operand pair into acc, software pipelined so that
+// LDS traffic, global loads and the barrier overlap the MFMAs.  Per step i
+// (one BK slice, its MFMA sub-steps taken in pairs):
+//   * the fragments of the next pair are read while the current pair's
+//     MFMAs issue;
+//   * after the first pair(s), slice i+1 (loaded into registers during step
+//     i-1) is stored into the other LDS buffer and the global loads of slice
+//     i+2 are issued, so every load has a whole step to arrive;
+//   * the one barrier per step sits before the last pair, whose MFMAs cover
+//     the reads of slice i+1's first pair from the other buffer.
+// The order of the products into every accumulator is the plain k order,
+// as in mma_loop_flat.
+template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0>
+__device__ __forceinline__ void mma_loop_pp(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
+                                            int N, int64_t kbeg, int64_t kend, T* smem,
+                                            typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI],
+                                            FoldAcc<Cfg>* fold = nullptr) {
+  typedef Lds<T, LA, BM, BK> LA_;
+  typedef Lds<T, LB, BN, BK> LB_;
+  constexpr int STAGE = LA_::SIZE + LB_::SIZE;
+  constexpr int NPAIR = BK / 8;  // pairs of MFMA sub-steps per slice
+  static_assert(NPAIR % 2 == 0, "pairs");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int wm = wv / (BN / Cfg::WTN);
+  const int wn = wv % (BN / Cfg::WTN);
+  typedef Stager<T, TA, LA, BM, BK, Cfg::THREADS> SA;
+  typedef Stager<T, TB, LB, BN, BK, Cfg::THREADS> SB;
+  SA sa;
+  SB sb;
+  const int64_t rowa = SA::row_of(A, m0, M, tid);
+  const int64_t rowb = SB::row_of(B, n0, N, tid);
+  const bool ala = SA::aligned(A), alb = SB::aligned(B);
+  if (kbeg >= kend) return;
+  const int xa = wm * Cfg::WTM + (lane & 15), xb = wn * Cfg::WTN + (lane & 15);
+  sa.load(A, m0, M, kbeg, kend, tid, rowa, ala);
+  sb.load(B, n0, N, kbeg, kend, tid, rowb, alb);
+  sa.store(smem, tid);
+  sb.store(smem + LA_::SIZE, tid);
+  if (kbeg + BK < kend) {
+    sa.load(A, m0, M, kbeg + BK, kend, tid, rowa, ala);
+    sb.load(B, n0, N, kbeg + BK, kend, tid, rowb, alb);
+  }
+  __syncthreads();
+  T fa[2][Cfg::MI][2], fb[2][Cfg::NI][2];  // fragments of two sub-step pairs
+#pragma unroll
+  for (int i = 0; i < Cfg::MI; ++i) read2<T, LA, BM, BK>(smem, xa + i * 16, 0, 0, lane, fa[0][i]);
+#pragma unroll
+  for (int j = 0; j < Cfg::NI; ++j) read2<T, LB, BN, BK>(smem + LA_::SIZE, xb + j * 16, 0, 0, lane, fb[0][j]);
+  int cur = 0;
+  int step = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool next = k0 + BK < kend;
+    const T* cbuf = smem + cur * STAGE;
+    T* nbuf = smem + (cur ^ 1) * STAGE;
+#pragma unroll
+    for (int p = 0; p < NPAIR; ++p) {
+      const int sl = p & 1, nsl = sl ^ 1;
+      if (p + 1 < NPAIR) {
+        const int c = (p + 1) >> 1, s0 = 2 * ((p + 1) & 1);
+#pragma unroll
+        for (int i = 0; i < Cfg::MI; ++i) read2<T, LA, BM, BK>(cbuf, xa + i * 16, c, s0, lane, fa[nsl][i]);
+#pragma unroll
+        for (int j = 0; j < Cfg::NI; ++j)
+          read2<T, LB, BN, BK>(cbuf + LA_::SIZE, xb + j * 16, c, s0, lane, fb[nsl][j]);
+      } else {
+        __syncthreads();  // slice i+1 stored by every wave; reads of this buffer done
+        if (next) {
+#pragma unroll
+          for (int i = 0; i < Cfg::MI; ++i) read2<T, LA, BM, BK>(nbuf, xa + i * 16, 0, 0, lane, fa[nsl][i]);
+#pragma unroll
+          for (int j = 0; j < Cfg::NI; ++j)
+            read2<T, LB, BN, BK>(nbuf + LA_::SIZE, xb + j * 16, 0, 0, lane, fb[nsl][j]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+          for (int j = 0; j < Cfg::NI; ++j) MfmaT<T>::mma(fa[sl][i][t], fb[sl][j][t], acc[i][j]);
+      __builtin_amdgcn_sched_barrier(0);  // keep each pair's MFMAs in place
+      if (p == NPAIR - 2 && next) {
+        // slice i+1 (in registers since step i-1) into the other buffer, whose
+        // last reads finished before the previous barrier; then the loads of
+        // slice i+2, which have a whole step to arrive
+        sa.store(nbuf, tid);
+        sb.store(nbuf + LA_::SIZE, tid);
+        if (k0 + 2 * BK < kend) {
+          sa.load(A, m0, M, k0 + 2 * BK, kend, tid, rowa, ala);
+          sb.load(B, n0, N, k0 + 2 * BK, kend, tid, rowb, alb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if constexpr (FOLD > 0) {
+      if (++step == FOLD) {
+        step = 0;
+        fold_into<Cfg>(acc, *fold);
+      }
+    }
+    cur ^= 1;
+  }
+  if constexpr (FOLD > 0) fold_into<Cfg>(acc, *fold);
+}
+
 // Runs the K loop of one operand pair into acc.  LDS is double buffered:
 // the slice for step i+1 is loaded from global memory while step i feeds the
 // MFMAs, stored into the other buffer, and one barrier per step separates
@@ -264,7 +388,7 @@ __device__ __forceinline__ void fold_into(A (&acc)[Cfg::MI][Cfg::NI], FoldAcc<Cf
 // and cleared every FOLD steps and at the end, so FP32 rounding of the
 // running sums does not grow with K.
 template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0>
-__device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
+__device__ __forceinline__ void mma_loop_flat(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
                                          int N, int64_t kbeg, int64_t kend, T* smem,
                                          typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI],
                                          FoldAcc<Cfg>* fold = nullptr) {
@@ -328,6 +452,19 @@ __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>
     cur ^= 1;
   }
   if constexpr (FOLD > 0) fold_into<Cfg>(acc, *fold);
+}
+
+// The K loop of one operand pair: the software-pipelined form, except for
+// folded FP32 accumulators, whose extra FP64 set leaves no registers for it.
+template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0>
+__device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
+                                         int N, int64_t kbeg, int64_t kend, T* smem,
+                                         typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI],
+                                         FoldAcc<Cfg>* fold = nullptr) {
+  if constexpr (FOLD > 0)
+    mma_loop_flat<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD>(A, B, m0, n0, M, N, kbeg, kend, smem, acc, fold);
+  else
+    mma_loop_pp<Cfg, T, TA, LA, TB, LB, BM, BN, BK, 0>(A, B, m0, n0, M, N, kbeg, kend, smem, acc, fold);
 }
 
 // Tile coordinates handed to epilogues.
