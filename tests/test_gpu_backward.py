@@ -245,3 +245,59 @@ def test_backward_split_precision_complex(prec):
     tol = max(1e-5, 1e-7 * kappa)
     assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
     assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
+
+
+@pytest.mark.parametrize("general", [True, False])
+def test_backward_from_kept_gram_blocks_upstream(general):
+    """isdf_zc_ab + isdf_fit_backward_gram with a random upstream gradient
+    (not the fused loss), ragged r-blocks of 50 rows: the same gradients as
+    isdf_fit_backward bit for bit, and the oracle's within the FP64 bar."""
+    from paper_2208_07731_amd import _lib as L
+    import ctypes as C
+
+    lib = L.load()
+    rng, big, idx = tiny(13 + general)
+    nr, n_mu = big.shape[0], len(idx)
+    phi = big[:, :7]
+    psi = big[:, 7:16] if general else phi
+    t = dev(big)
+    tp = t[:, :7]
+    ts = t[:, 7:16] if general else tp
+    if general:
+        tbar = rng.standard_normal((nr, n_mu)) + 1j * rng.standard_normal((nr, n_mu))
+    else:
+        tbar = rng.standard_normal((nr, n_mu))
+    ref = oracle.fit_backward(phi, psi, idx, theta_bar=tbar)
+    idx_t = dev(idx)
+    _, minv, _ = isdf.fit(tp, ts if general else None, idx_t, grid=(5, 6, 7), nrows=0)
+    tb = dev(tbar)
+    want = isdf.fit_backward(tp, ts if general else None, idx_t, minv, theta_bar=tb, grid=(5, 6, 7), rblock=50)
+    n1 = 2 * n_mu if general else n_mu
+    G = torch.empty(nr, n1, dtype=torch.float64, device="cuda")
+    A = torch.empty(nr, 2 * n_mu, dtype=torch.float64, device="cuda")
+    B = torch.empty(nr, 2 * n_mu, dtype=torch.float64, device="cuda") if general else None
+    g = L.make_grid((5, 6, 7))
+    s = torch.cuda.current_stream().cuda_stream
+    ld_p, n_p = tp.stride(0), tp.shape[1]
+    ld_s, n_s = ts.stride(0), ts.shape[1]
+    zws = torch.empty(lib.isdf_zc_workspace(n_mu, n_p, n_s, int(not general), 0, nr), dtype=torch.uint8, device="cuda")
+    assert lib.isdf_zc_ab(C.byref(g), L.C128, tp.data_ptr(), ld_p, n_p, ts.data_ptr(), ld_s, n_s, idx_t.data_ptr(),
+                          n_mu, 0, 0, nr, G.data_ptr(), n1, A.data_ptr(), None if B is None else B.data_ptr(),
+                          zws.data_ptr(), zws.numel(), s) == L.OK
+    bws = torch.empty(lib.isdf_fit_backward_gram_workspace(C.byref(g), n_mu, n_p, n_s, int(not general), 0, 50),
+                      dtype=torch.uint8, device="cuda")
+    dphi = torch.empty(nr, n_p, dtype=torch.complex128, device="cuda")
+    dpsi = torch.empty(nr, n_s, dtype=torch.complex128, device="cuda") if general else dphi
+    info = torch.zeros(C.sizeof(L.FitInfo), dtype=torch.uint8, device="cuda")
+    assert lib.isdf_fit_backward_gram(C.byref(g), L.C128, tp.data_ptr(), ld_p, n_p, ts.data_ptr(), ld_s, n_s,
+                                      idx_t.data_ptr(), n_mu, 0, minv.data_ptr(), tb.data_ptr(), n_mu, None,
+                                      dphi.data_ptr(), n_p, dpsi.data_ptr(), n_s, None, 50, G.data_ptr(),
+                                      A.data_ptr(), None if B is None else B.data_ptr(), info.data_ptr(),
+                                      bws.data_ptr(), bws.numel(), s) == L.OK
+    torch.cuda.synchronize()
+    assert torch.equal(dphi, want[0])
+    if general:
+        assert torch.equal(dpsi, want[1])
+    kappa = oracle.cc_condition(phi, psi, idx)
+    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
