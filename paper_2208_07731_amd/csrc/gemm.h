@@ -137,6 +137,7 @@ struct Stager {
   static constexpr int E = X * BK / THREADS;
   static_assert(E % 2 == 0, "pairs");
   T v[E];
+  double fk;  // XC: scale of this thread's k row (1 without scales)
   __device__ __forceinline__ void load(const Operand<TS>& op, int x0, int xlim, int64_t k0, int64_t klim, int tid,
                                        int64_t rowcache, bool aligned) {
     const bool interior = aligned && (x0 + X <= xlim) && (k0 + BK <= klim);
@@ -174,22 +175,26 @@ struct Stager {
       const int64_t k = k0 + tid / RUNS;
       const int xb = x0 + 2 * (tid % RUNS);
       const TS* base = op.p + k * op.ld + xb;
-      const double f = (op.kscale && k < klim) ? op.kscale[k] : 1.0;
+      // the row scale is applied when the slice is stored, so that nothing
+      // waits for these loads before then (elements outside the operand are
+      // zero, so a clamped row index is enough for theirs)
+      fk = 1.0;
+      if (op.kscale) fk = op.kscale[k < klim ? k : klim - 1];
       if (interior) {
 #pragma unroll
         for (int c = 0; c < E / 2; ++c) {
           double a, b;
           load_pair<TS>(base + 2 * RUNS * c, a, b);
-          v[2 * c] = (T)(a * f);
-          v[2 * c + 1] = (T)(b * f);
+          v[2 * c] = (T)a;
+          v[2 * c + 1] = (T)b;
         }
       } else {
         const bool okk = k < klim;
 #pragma unroll
         for (int c = 0; c < E / 2; ++c) {
           const int x = xb + 2 * RUNS * c;
-          v[2 * c] = (okk && x < xlim) ? (T)(base[2 * RUNS * c] * f) : (T)0;
-          v[2 * c + 1] = (okk && x + 1 < xlim) ? (T)(base[2 * RUNS * c + 1] * f) : (T)0;
+          v[2 * c] = (okk && x < xlim) ? (T)base[2 * RUNS * c] : (T)0;
+          v[2 * c + 1] = (okk && x + 1 < xlim) ? (T)base[2 * RUNS * c + 1] : (T)0;
         }
       }
     }
@@ -206,8 +211,8 @@ struct Stager {
       T* d = s + L::at(2 * (tid % RUNS), tid / RUNS);
 #pragma unroll
       for (int c = 0; c < E / 2; ++c) {
-        d[2 * RUNS * c] = v[2 * c];
-        d[2 * RUNS * c + 1] = v[2 * c + 1];
+        d[2 * RUNS * c] = (T)(v[2 * c] * fk);
+        d[2 * RUNS * c + 1] = (T)(v[2 * c + 1] * fk);
       }
     }
   }
