@@ -113,17 +113,20 @@ def test_step_general_psi_matches_api():
     assert st.loss.item() == loss.item()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x6", "fp16x3"])
+@pytest.mark.parametrize("prec,dtype", [("fp64", np.complex128), ("bf16x6", np.complex128),
+                                        ("fp16x3", np.complex128), ("fp32", np.complex64),
+                                        ("bf16x6", np.complex64)])
 @pytest.mark.parametrize("general", [False, True])
-def test_saved_gram_adjoint_bitwise(prec, general):
+def test_saved_gram_adjoint_bitwise(prec, dtype, general):
     """The adjoint from the forward's Gram blocks (isdf_zc_ab +
     isdf_fit_backward_gram) gives the recomputing adjoint's gradients and
-    loss bit for bit, with ragged backward r-blocks (rblock = 100)."""
+    loss bit for bit, with ragged backward r-blocks (rblock = 100), for
+    complex128 and complex64 orbitals."""
     rng = np.random.default_rng(92 + general)
     n = (6, 7, 8)
     nr = 336
     big = rng.standard_normal((nr, 14)) + 1j * rng.standard_normal((nr, 14))
-    t = dev(big)
+    t = dev(big.astype(dtype))
     phi = t[:, :5]
     psi = t[:, 5:14] if general else None
     g = dev(rng.uniform(0.5, 1.5, nr))
