@@ -205,7 +205,8 @@ int isdf_zc(const isdf_grid* grid /* host */, isdf_dtype dt,
             void* ws, size_t ws_bytes, void* stream);
 
 /*
- * isdf_zc_ab: isdf_zc that also keeps the Gram blocks of the same rows,
+ * isdf_zc_ab: isdf_zc that also keeps the Gram blocks of the same rows
+ * (the P^phi and P^psi of eq. muRownuColden),
  *   A = Phi Phi_mu^H and (Psi != Phi only) B = Psi Psi_mu^H,
  * as [nrows][2 n_mu] interleaved complex FP64 (ld 2 n_mu), for
  * isdf_fit_backward_gram.  Same workspace as isdf_zc.  B is unused (may be
