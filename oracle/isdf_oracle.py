@@ -54,7 +54,7 @@ __all__ = [
     "assign", "update", "snap", "kmeans", "gather", "gram_blocks", "hadamard",
     "fit", "fit_theta", "fit_backward", "fit_residual", "cluster_residual",
     "cc_condition", "explicit_z", "reciprocal_sq", "poisson", "exchange", "exchange_direct",
-    "qrcp", "qrcp_greedy_excess", "qrcp_sampled_check",
+    "qrcp", "qrcp_sketch", "khatri_rao_sketch", "qrcp_greedy_excess", "qrcp_sampled_check",
 ]
 
 # --------------------------------------------------------------------------
@@ -392,26 +392,12 @@ def _suffix_sq(w: np.ndarray) -> np.ndarray:
     return np.cumsum(a[::-1], axis=0)[::-1]
 
 
-def qrcp(phi: np.ndarray, psi: np.ndarray, n_mu: int, rtol: float = 1e-7) -> dict:
-    """Interpolation points from the QR factorisation with column pivoting
-    of Z^T (Sec. 2.1, eq. QRCP): Z^T Pi = Q R with |R_kk| non-increasing; the
-    first n_mu pivot columns of Z^T (grid points) are the interpolation
-    points.  Z is formed explicitly (tiny inputs only) and factored by
-    LAPACK's pivoted Householder QR (geqp3).  The paper's baseline is a
-    randomized QRCP that approximates these pivots from a sketch of Z^T; this
-    is the exact factorisation it approximates.
-
-    Returns dict:
-      idx    [n_mu] int64 grid index of pivot k; -1 from the numerical rank on
-      rdiag  [n_mu] |R_kk| (0 from the rank on)
-      gap    [n_mu] (s_1 - s_2) / s_1 with s_1 >= s_2 the two largest squared
-             residual column norms at step k: the margin of the pivot choice
-      rank   number of k < n_mu with |R_kk| > rtol |R_00|
-    Exact ties follow LAPACK's column order (not necessarily lowest index).
-    """
-    zt = explicit_z(phi, psi).T                     # (N_phi N_psi) x N_r
-    r, piv = sla.qr(zt, mode="r", pivoting=True)
-    m = min(zt.shape)
+def _qrcp_columns(mt: np.ndarray, n_mu: int, rtol: float) -> dict:
+    """Pivoted Householder QR (LAPACK geqp3) of a matrix whose columns are
+    the grid points: returns the first n_mu pivots with |R_kk|, decision
+    margins and numerical rank, as documented in qrcp()."""
+    r, piv = sla.qr(mt, mode="r", pivoting=True)
+    m = min(mt.shape)
     r = r[:m]
     kmax = min(n_mu, m)
     s = _suffix_sq(r)
@@ -432,19 +418,67 @@ def qrcp(phi: np.ndarray, psi: np.ndarray, n_mu: int, rtol: float = 1e-7) -> dic
     return dict(idx=idx, rdiag=rdiag, gap=gap, rank=rank)
 
 
-def qrcp_greedy_excess(phi: np.ndarray, psi: np.ndarray, idx) -> np.ndarray:
-    """Brute-force check of the pivot rule behind eq. QRCP for a given pivot
-    order: with Q_k an orthonormal basis of the first k chosen columns of
-    Z^T, pivot k must have the largest norm of (I - Q_k Q_k^H) z over all
-    columns z.  Returns, per step, (max_z s_k(z) - s_k(idx[k])) / s_0(idx[0]),
-    which is >= 0 up to rounding and 0 for a greedy order.  Tiny inputs only.
-    A property test: `idx` may come from any implementation."""
+def qrcp(phi: np.ndarray, psi: np.ndarray, n_mu: int, rtol: float = 1e-7) -> dict:
+    """Interpolation points from the QR factorisation with column pivoting
+    of Z^T (Sec. 2.1, eq. QRCP): Z^T Pi = Q R with |R_kk| non-increasing; the
+    first n_mu pivot columns of Z^T (grid points) are the interpolation
+    points.  Z is formed explicitly (tiny inputs only) and factored by
+    LAPACK's pivoted Householder QR (geqp3).  The paper's baseline is a
+    randomized QRCP that approximates these pivots from a sketch of Z^T
+    (qrcp_sketch); this is the exact factorisation it approximates.
+
+    Returns dict:
+      idx    [n_mu] int64 grid index of pivot k; -1 from the numerical rank on
+      rdiag  [n_mu] |R_kk| (0 from the rank on)
+      gap    [n_mu] (s_1 - s_2) / s_1 with s_1 >= s_2 the two largest squared
+             residual column norms at step k: the margin of the pivot choice
+      rank   number of k < n_mu with |R_kk| > rtol |R_00|
+    Exact ties follow LAPACK's column order (not necessarily lowest index).
+    """
+    return _qrcp_columns(explicit_z(phi, psi).T, n_mu, rtol)   # (N_phi N_psi) x N_r
+
+
+def khatri_rao_sketch(g_phi: np.ndarray, g_psi: np.ndarray) -> np.ndarray:
+    """Omega [(i, j)][k] = g_phi[i, k] g_psi[j, k]: the column-wise Kronecker
+    (Khatri-Rao) product of two random matrices, the test matrix that maps
+    the N_phi N_psi rows of Z^T to m sketch rows."""
+    return (g_phi[:, None, :] * g_psi[None, :, :]).reshape(-1, g_phi.shape[1])
+
+
+def qrcp_sketch(phi: np.ndarray, psi: np.ndarray, n_mu: int, g_phi: np.ndarray, g_psi: np.ndarray,
+                rtol: float = 1e-7) -> dict:
+    """Randomized QRCP (Sec. 1 and Sec. 2.1: the standard IP selection the
+    paper compares against): the pivoted QR of eq. QRCP applied to the
+    sketch (Z Omega)^T, m x N_r, instead of Z^T, with Omega the Khatri-Rao
+    product of the real random matrices g_phi [N_phi][m] and g_psi
+    [N_psi][m] (the random numbers are inputs).  Z Omega is formed
+    explicitly from Z here; its entry (r, k) equals
+    (Phi g_phi[:, k])(r) conj((Psi g_psi[:, k])(r)).  Same return value as
+    qrcp()."""
+    y = explicit_z(phi, psi) @ khatri_rao_sketch(g_phi, g_psi)   # N_r x m
+    return _qrcp_columns(y.T, n_mu, rtol)
+
+
+def _greedy_excess(mt: np.ndarray, idx) -> np.ndarray:
     idx = np.asarray(idx)
-    zt = explicit_z(phi, psi).T
-    q, _ = np.linalg.qr(zt[:, idx], mode="complete")
-    s = _suffix_sq(q.conj().T @ zt)
+    q, _ = np.linalg.qr(mt[:, idx], mode="complete")
+    s = _suffix_sq(q.conj().T @ mt)
     ex = np.array([s[k].max() - s[k, idx[k]] for k in range(len(idx))])
     return ex / s[0, idx[0]]
+
+
+def qrcp_greedy_excess(phi: np.ndarray, psi: np.ndarray, idx, g_phi=None, g_psi=None) -> np.ndarray:
+    """Brute-force check of the pivot rule behind eq. QRCP for a given pivot
+    order: with Q_k an orthonormal basis of the first k chosen columns of
+    Z^T (or of the sketch (Z Omega)^T when g_phi, g_psi are given), pivot k
+    must have the largest norm of (I - Q_k Q_k^H) z over all columns z.
+    Returns, per step, (max_z s_k(z) - s_k(idx[k])) / s_0(idx[0]), which is
+    >= 0 up to rounding and 0 for a greedy order.  Tiny inputs only.  A
+    property test: `idx` may come from any implementation."""
+    z = explicit_z(phi, psi)
+    if g_phi is not None:
+        z = z @ khatri_rao_sketch(g_phi, g_psi)
+    return _greedy_excess(z.T, idx)
 
 
 def qrcp_sampled_check(phi: np.ndarray, psi: np.ndarray, idx, rdiag, rows) -> dict:

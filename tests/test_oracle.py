@@ -666,3 +666,53 @@ def test_qrcp_permutation_and_gauge_equivariant():
     og = oracle.qrcp(phi @ haar_unitary(rng, 4), psi @ haar_unitary(rng, 5), 15)
     assert np.array_equal(og["idx"], o["idx"])
     assert np.allclose(og["rdiag"], o["rdiag"], rtol=1e-12, atol=0)
+
+
+def _sketch_mats(rng, n_phi, n_psi, m):
+    return rng.standard_normal((n_phi, m)), rng.standard_normal((n_psi, m))
+
+
+def test_qrcp_sketch_is_hadamard_of_products():
+    """(Z Omega)(r, k) = (Phi g_phi[:, k])(r) conj((Psi g_psi[:, k])(r)) for the
+    Khatri-Rao Omega (explicit Z against the two thin products)."""
+    rng = np.random.default_rng(90)
+    phi, psi = _orth(rng, 60, 4), _orth(rng, 60, 5)
+    gp, gs = _sketch_mats(rng, 4, 5, 11)
+    y = oracle.explicit_z(phi, psi) @ oracle.khatri_rao_sketch(gp, gs)
+    y2 = (phi @ gp) * np.conj(psi @ gs)
+    assert np.max(np.abs(y - y2)) <= 1e-14 * np.max(np.abs(y))
+
+
+def test_qrcp_sketch_orthogonal_kronecker_is_exact():
+    """With m = N_phi N_psi and g_phi[:, (a, b)] = U[:, a], g_psi[:, (a, b)] = V[:, b]
+    for orthogonal U, V, Omega = U (x) V is orthogonal: the sketch keeps every
+    column norm and projection of Z^T, so its pivots and |R_kk| are those of
+    the exact QRCP."""
+    rng = np.random.default_rng(91)
+    n_phi, n_psi = 3, 4
+    phi, psi = _orth(rng, 150, n_phi), _orth(rng, 150, n_psi)
+    u = np.linalg.qr(rng.standard_normal((n_phi, n_phi)))[0]
+    v = np.linalg.qr(rng.standard_normal((n_psi, n_psi)))[0]
+    gp = np.repeat(u, n_psi, axis=1)          # column (a, b) -> U[:, a]
+    gs = np.tile(v, (1, n_phi))               # column (a, b) -> V[:, b]
+    om = oracle.khatri_rao_sketch(gp, gs)
+    assert np.allclose(om.T @ om, np.eye(n_phi * n_psi), atol=1e-13)
+    ex = oracle.qrcp(phi, psi, 10)
+    sk = oracle.qrcp_sketch(phi, psi, 10, gp, gs)
+    assert ex["gap"].min() > 1e-8
+    assert np.array_equal(sk["idx"], ex["idx"])
+    assert np.allclose(sk["rdiag"], ex["rdiag"], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("aliased", [True, False])
+def test_qrcp_sketch_is_greedy_on_the_sketch(aliased):
+    """The sketch pivots are greedy on (Z Omega)^T (brute force), rank is
+    capped by m, and they differ from the exact pivots only through Omega."""
+    rng = np.random.default_rng(92 + aliased)
+    phi = _orth(rng, 300, 5)
+    psi = phi if aliased else _orth(rng, 300, 4)
+    gp, gs = _sketch_mats(rng, 5, psi.shape[1], 14)
+    sk = oracle.qrcp_sketch(phi, psi, 18, gp, gs, rtol=1e-10)
+    assert sk["rank"] == 14 and np.all(sk["idx"][14:] == -1)
+    ex = oracle.qrcp_greedy_excess(phi, psi, sk["idx"][:14], gp, gs)
+    assert ex.max() <= 1e-12 and ex.min() >= -1e-12
