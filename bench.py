@@ -164,9 +164,12 @@ def qrcp_leg(phi, psi, wl, km_idx, km_ms, steps) -> dict:
     algorithmic HBM bytes (each of the N_mu - 1 column steps reads the
     orbitals and the first k columns of L and writes column k and the
     residual diagonal), and the FP64 fit's least-squares residual at the QRCP
-    points beside the K-means points'."""
+    points beside the K-means points'; then the randomized QRCP of a
+    Khatri-Rao sketch of Z^T with N_mu + 8 rows (isdf_qrcp_sketch), timed and
+    fitted the same way."""
     import math
 
+    import numpy as np
     import torch
 
     from paper_2208_07731_amd import api
@@ -191,7 +194,23 @@ def qrcp_leg(phi, psi, wl, km_idx, km_ms, steps) -> dict:
            "frac": round(nbytes / ms / 1e6 / HBM_PEAK, 4), "rank": r.info["rank"],
            "near_ties": r.info["near_ties"], "r_last_over_r00": float(r.rdiag[-1] / r.rdiag[0]),
            "kmeans_ms": km_ms, "qrcp_over_kmeans_time": round(ms / km_ms, 1) if km_ms else None}
-    for name, idx in (("qrcp", r.idx), ("kmeans", km_idx)):
+    # randomized QRCP (Khatri-Rao sketch with m = N_mu + 8 rows, seeded normal)
+    m = wl.n_mu + 8
+    rng = np.random.default_rng(1000 * wl.cfg + 6)
+    gp = torch.as_tensor(rng.standard_normal((wl.n_phi, m))).cuda()
+    gs = torch.as_tensor(rng.standard_normal((wl.n_psi, m))).cuda()
+    api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n, sketch=(gp, gs))
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        rs = api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n, sketch=(gp, gs))
+    b.record()
+    torch.cuda.synchronize()
+    ms_s = a.elapsed_time(b) / steps
+    out["sketch"] = {"m": m, "ms": round(ms_s, 2), "rank": rs.info["rank"],
+                     "pivots_shared_with_exact": int(np.intersect1d(rs.idx.cpu().numpy(),
+                                                                    r.idx.cpu().numpy()).size)}
+    for name, idx in (("qrcp", r.idx), ("qrcp_sketch", rs.idx), ("kmeans", km_idx)):
         idx = idx[idx >= 0].contiguous()
         _, minv, info = api.fit(phi, psi_arg, idx, nrows=0)
         res, zz = api.fit_residual(phi, psi_arg, idx, minv, rblock=wl.rblock or None)

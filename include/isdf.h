@@ -416,6 +416,34 @@ int isdf_qrcp(const isdf_grid* grid /* host */, isdf_dtype dt,
               int32_t* idx, double* rdiag, double* gap, isdf_qrcp_info* info,
               void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Randomized QRCP (Sec. 1 and Sec. 2.1: the standard IP selection the paper
+ * compares against): the pivoted QR of eq. QRCP applied to the sketch
+ * (Z Omega)^T (m x N_r) instead of Z^T, with Omega the Khatri-Rao product
+ *   Omega[(i, j)][k] = g_phi[i][k] g_psi[j][k],
+ * so that X = Z Omega = (Phi g_phi) .* conj(Psi g_psi) (N_r x m, one FP64
+ * Hadamard Gram product of the fit's kind, two right-hand sides even when
+ * psi == phi); then the pivots of the pivoted Cholesky of X X^H, as in
+ * isdf_qrcp.
+ *   g_phi [n_phi][m], g_psi [n_psi][m]  FP64 device: the random numbers
+ *        (the caller draws them, e.g. standard normal)
+ *   m    sketch size, 1 <= m <= 3072; at most m pivots exist, so m >= n_mu
+ *        for a full set
+ *   other arguments and outputs as isdf_qrcp.
+ * Cost: 8 N_r m (N_phi + N_psi) flops for X, then n_mu passes over X and
+ * over L: more than isdf_qrcp whenever m > (N_phi + N_psi) / 2.  Workspace:
+ * isdf_qrcp_sketch_workspace bytes (X, [N_r][m] complex, plus a complex L).
+ */
+size_t isdf_qrcp_sketch_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                                  int32_t m);
+int isdf_qrcp_sketch(const isdf_grid* grid /* host */, isdf_dtype dt,
+                     const void* phi, int64_t ld_phi, int32_t n_phi,
+                     const void* psi, int64_t ld_psi, int32_t n_psi,
+                     const double* g_phi, const double* g_psi, int32_t m,
+                     int32_t n_mu, double rtol, double near_tie_rel,
+                     int32_t* idx, double* rdiag, double* gap, isdf_qrcp_info* info,
+                     void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* isdf_version(void);
 const char* isdf_strerror(int status);

@@ -80,6 +80,9 @@ SIGNATURES = {
     "isdf_qrcp_workspace": (_SZ, [_G, _I32, _I32]),
     "isdf_qrcp": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _SZ,
                             _P]),
+    "isdf_qrcp_sketch_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32]),
+    "isdf_qrcp_sketch": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _P, _I32, _I32, _D, _D, _P, _P,
+                                   _P, _P, _P, _SZ, _P]),
     "isdf_cluster_residual_workspace": (_SZ, []),
     "isdf_cluster_residual": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _P, _I32, _P, _P, _SZ,
                                         _P]),

@@ -137,9 +137,11 @@ class QRCPResult:
 
 
 def qrcp(phi: torch.Tensor, psi: torch.Tensor | None, n_mu: int, *, rtol: float = 1e-7,
-         near_tie_rel: float = 1e-9, grid=None) -> QRCPResult:
+         near_tie_rel: float = 1e-9, grid=None, sketch=None) -> QRCPResult:
     """Interpolation points by QR with column pivoting of Z^T (isdf_qrcp,
-    eq. QRCP), Z never formed.  psi None or psi is phi: the aliased path."""
+    eq. QRCP), Z never formed.  psi None or psi is phi: the aliased path.
+    sketch=(g_phi, g_psi), float64 device tensors [N_phi][m] and [N_psi][m]:
+    the randomized QRCP of the Khatri-Rao sketch (isdf_qrcp_sketch)."""
     lib = L.load()
     if psi is None:
         psi = phi
@@ -154,12 +156,26 @@ def qrcp(phi: torch.Tensor, psi: torch.Tensor | None, n_mu: int, *, rtol: float 
     rdiag = torch.empty(n_mu, dtype=torch.float64, device=dev)
     gap = torch.empty(n_mu, dtype=torch.float64, device=dev)
     info = torch.zeros(C.sizeof(L.QrcpInfo), dtype=torch.uint8, device=dev)
-    wsb = lib.isdf_qrcp_workspace(C.byref(g), n_mu, int(_same(phi, psi)))
-    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
-    code = lib.isdf_qrcp(C.byref(g), dt, pp, lp, npf, ps, lps, nps, n_mu, rtol, near_tie_rel, idx.data_ptr(),
-                         rdiag.data_ptr(), gap.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
-                         _stream_handle())
-    _check(code, "isdf_qrcp")
+    if sketch is None:
+        wsb = lib.isdf_qrcp_workspace(C.byref(g), n_mu, int(_same(phi, psi)))
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+        code = lib.isdf_qrcp(C.byref(g), dt, pp, lp, npf, ps, lps, nps, n_mu, rtol, near_tie_rel, idx.data_ptr(),
+                             rdiag.data_ptr(), gap.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                             _stream_handle())
+        _check(code, "isdf_qrcp")
+    else:
+        gp, gs = sketch
+        m = gp.shape[1]
+        for t, n in ((gp, npf), (gs, nps)):
+            if t.dtype != torch.float64 or t.device != dev or not t.is_contiguous() or t.shape != (n, m):
+                raise TypeError("sketch matrices must be contiguous float64 (N_phi, m) and (N_psi, m) on the "
+                                "orbitals' device")
+        wsb = lib.isdf_qrcp_sketch_workspace(C.byref(g), n_mu, npf, nps, m)
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+        code = lib.isdf_qrcp_sketch(C.byref(g), dt, pp, lp, npf, ps, lps, nps, gp.data_ptr(), gs.data_ptr(), m, n_mu,
+                                    rtol, near_tie_rel, idx.data_ptr(), rdiag.data_ptr(), gap.data_ptr(),
+                                    info.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle())
+        _check(code, "isdf_qrcp_sketch")
     torch.cuda.current_stream().synchronize()
     inf = _read_struct(info, L.QrcpInfo)
     if inf.status != L.OK:

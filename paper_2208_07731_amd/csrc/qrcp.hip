@@ -13,20 +13,36 @@
 // an O(N_r (N_phi + N_psi + k)) pass over the orbitals and the first k
 // columns of L: HBM-bound, N_mu dependent passes, O(N_mu^2 N_r) in total.
 //
-// Kernels: qrcp_init (d = rho_phi rho_psi and workgroup top-2 partials),
-// qrcp_select (one workgroup: global top-2, accept or stop, gather the next
-// pivot's row of L) and qrcp_step (one column of L).  Everything a step needs
-// lives in device memory, so the host enqueues all 2 N_mu launches without
-// synchronising; after a stop every later launch returns at once.
-#include "common.h"
+// The randomized variant factors the sketch (Z Omega)^T instead of Z^T, with
+// Omega the Khatri-Rao product of random g_phi [N_phi][m], g_psi [N_psi][m]:
+// X = Z Omega = (Phi g_phi) .* conj(Psi g_psi) (N_r x m) is one Hadamard Gram
+// product of the fit's kind (the random columns in place of the orbital rows
+// at the interpolation points), and the same pivoted Cholesky runs on the
+// plain Gram matrix X X^H, whose column p is X conj(X(p))^T.
+//
+// Kernels: qrcp_init (d = the diagonal of the Gram matrix and workgroup top-2
+// partials), qrcp_select (one workgroup: global top-2, accept or stop, gather
+// the next pivot's row of L) and qrcp_step (one column of L).  Everything a
+// step needs lives in device memory, so the host enqueues all 2 N_mu launches
+// without synchronising; after a stop every later launch returns at once.
+#include <algorithm>
+
+#include "fitlib.h"
 
 namespace isdf {
 namespace {
 
 constexpr int QR_TILE = 256;     // grid rows per workgroup (one per thread in phase 2)
 constexpr int QR_LPC = 1024;     // pivot-row entries staged in LDS per chunk
-constexpr int QR_SEL = 1024;     // threads of qrcp_select
+constexpr int QR_SEL = 256;      // threads of qrcp_select
 constexpr int QR_UNROLL = 4;     // rows per wavefront in flight in phase 1
+
+// Gram matrix K whose pivoted Cholesky is taken:
+enum {
+  QR_ALIASED = 0,  // K = |Phi Phi^H|^2 (Psi = Phi): real
+  QR_HADAMARD = 1, // K = (Phi Phi^H) .* conj(Psi Psi^H): complex Hermitian
+  QR_PLAIN = 2     // K = X X^H (X passed as Phi): complex Hermitian
+};
 
 struct QrcpState {
   int32_t p;          // current pivot grid index
@@ -111,11 +127,12 @@ __device__ __forceinline__ double row_norm2(const TS* __restrict__ x, int64_t ld
   return wave_sum(a);
 }
 
-// d_r = rho_phi(r) rho_psi(r) = K(r, r) = |Z(r)|^2.  One wavefront per row.
+// d_r = K(r, r): rho_phi(r) rho_psi(r) = |Z(r)|^2, or |X(r)|^2 (QR_PLAIN).
+// One wavefront per row.
 template <class TS>
 __global__ __launch_bounds__(QR_TILE) void qrcp_init(const TS* __restrict__ phi, int64_t ldp, int nphi,
                                                     const TS* __restrict__ psi, int64_t lds, int npsi,
-                                                    int aliased, int64_t nr, double* __restrict__ d,
+                                                    int mode, int64_t nr, double* __restrict__ d,
                                                     double* __restrict__ part) {
   const int lane = threadIdx.x & (ISDF_WAVE - 1);
   const int wv = threadIdx.x / ISDF_WAVE;
@@ -125,7 +142,7 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_init(const TS* __restrict__ phi,
     const int64_t r = base + rr;
     if (r >= nr) break;
     const double a = row_norm2<TS>(phi, ldp, nphi, r, lane);
-    const double b = aliased ? a : row_norm2<TS>(psi, lds, npsi, r, lane);
+    const double b = mode == QR_ALIASED ? a : (mode == QR_PLAIN ? 1.0 : row_norm2<TS>(psi, lds, npsi, r, lane));
     if (lane == rr) mine = a * b;
   }
   const int64_t r = base + lane;
@@ -146,7 +163,7 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_init(const TS* __restrict__ phi,
 // the orbitals, Phi(p) and Psi(p) from LDS).  Phase 2: one thread per row
 // for the projection on the earlier columns (column-major L, coalesced; the
 // pivot's row of L broadcast from LDS in chunks).
-template <class TS, bool CPLX>
+template <class TS, int MODE>
 __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi, int64_t ldp, int nphi,
                                                     const TS* __restrict__ psi, int64_t lds, int npsi,
                                                     int64_t nr, int k, const QrcpState* __restrict__ st,
@@ -154,10 +171,12 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi,
                                                     const double* __restrict__ lp, double* __restrict__ part) {
   if (st->done) return;  // uniform: written by the previous select launch
   extern __shared__ double lds_mem[];
+  constexpr bool CPLX = MODE != QR_ALIASED;
+  constexpr bool TWO = MODE == QR_HADAMARD;  // a second orbital set
   constexpr int CW = CPLX ? 2 : 1;
   double2* sphi = reinterpret_cast<double2*>(lds_mem);
   double2* spsi = sphi + nphi;
-  double* slp = reinterpret_cast<double*>(spsi + (CPLX ? npsi : 0));
+  double* slp = reinterpret_cast<double*>(spsi + (TWO ? npsi : 0));
   const int64_t p = st->p;
   const double dp = st->dp;
   const int tid = threadIdx.x;
@@ -165,11 +184,11 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi,
   const int wv = tid / ISDF_WAVE;
 
   for (int i = tid; i < nphi; i += QR_TILE) sphi[i] = Cplx<TS>::load(phi + 2 * (p * ldp + i));
-  if (CPLX)
+  if (TWO)
     for (int i = tid; i < npsi; i += QR_TILE) spsi[i] = Cplx<TS>::load(psi + 2 * (p * lds + i));
   __syncthreads();
 
-  // ---- phase 1: c = K(r, p) = a conj(b), a = Phi(r).conj(Phi(p)), b likewise
+  // ---- phase 1: c = K(r, p): a conj(b), |a|^2 or a, a = Phi(r).conj(Phi(p)), b likewise
   const int64_t base = (int64_t)blockIdx.x * QR_TILE + wv * ISDF_WAVE;
   double cre = 0.0, cim = 0.0;
   for (int rr = 0; rr < ISDF_WAVE; rr += QR_UNROLL) {
@@ -185,7 +204,7 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi,
           ar[u] += z.x * q.x + z.y * q.y;
           ai[u] += z.y * q.x - z.x * q.y;
         }
-        if (CPLX)
+        if (TWO)
           for (int i = lane; i < npsi; i += ISDF_WAVE) {
             const double2 z = Cplx<TS>::load(psi + 2 * (r * lds + i));
             const double2 q = spsi[i];
@@ -197,11 +216,16 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi,
 #pragma unroll
     for (int u = 0; u < QR_UNROLL; ++u) {
       const double sar = wave_sum(ar[u]), sai = wave_sum(ai[u]);
-      if (CPLX) {
+      if (TWO) {
         const double sbr = wave_sum(br[u]), sbi = wave_sum(bi[u]);
         if (lane == rr + u) {
           cre = sar * sbr + sai * sbi;  // a conj(b)
           cim = sai * sbr - sar * sbi;
+        }
+      } else if (MODE == QR_PLAIN) {
+        if (lane == rr + u) {
+          cre = sar;                    // X(r) . conj(X(p))
+          cim = sai;
         }
       } else if (lane == rr + u) {
         cre = sar * sar + sai * sai;    // |a|^2: Psi = Phi
@@ -397,8 +421,9 @@ __global__ void qrcp_reset(QrcpState* st) {
 }
 
 // LDS of one qrcp_step workgroup: Phi(p), Psi(p) and a chunk of the pivot's row of L.
-static size_t qrcp_lds_bytes(int n_phi, int n_psi, bool cplx) {
-  return sizeof(double2) * (size_t)(n_phi + (cplx ? n_psi : 0)) + sizeof(double) * QR_LPC * (cplx ? 2 : 1);
+static size_t qrcp_lds_bytes(int n_phi, int n_psi, int mode) {
+  return sizeof(double2) * (size_t)(n_phi + (mode == QR_HADAMARD ? n_psi : 0)) +
+         sizeof(double) * QR_LPC * (mode == QR_ALIASED ? 1 : 2);
 }
 static constexpr size_t QR_MAX_LDS = 64 * 1024;
 
@@ -425,24 +450,25 @@ static QrcpPlan plan_qrcp(void* ws, int64_t nr, int n_mu, bool cplx) {
   return pl;
 }
 
-template <class TS, bool CPLX>
+template <class TS, int MODE>
 static int qrcp_run(const TS* phi, int64_t ldp, int nphi, const TS* psi, int64_t lds, int npsi, int64_t nr, int n_mu,
                     double rtol, double near_tie_rel, int32_t* idx, double* rdiag, double* gap,
                     isdf_qrcp_info* info, const QrcpPlan& pl, hipStream_t s) {
   const int nblk = (int)ceil_div(nr, QR_TILE);
-  const size_t lds_bytes = qrcp_lds_bytes(nphi, npsi, CPLX);
+  constexpr bool CPLX = MODE != QR_ALIASED;
+  const size_t lds_bytes = qrcp_lds_bytes(nphi, npsi, MODE);
   const double rtol2 = rtol * rtol;
   hipLaunchKernelGGL(qrcp_reset, dim3(1), dim3(1), 0, s, pl.st);
   if (!launch_ok()) return ISDF_E_HIP;
-  hipLaunchKernelGGL((qrcp_init<TS>), dim3(nblk), dim3(QR_TILE), 0, s, phi, ldp, nphi, psi, lds, npsi,
-                     CPLX ? 0 : 1, nr, pl.d, pl.part);
+  hipLaunchKernelGGL((qrcp_init<TS>), dim3(nblk), dim3(QR_TILE), 0, s, phi, ldp, nphi, psi, lds, npsi, MODE, nr,
+                     pl.d, pl.part);
   if (!launch_ok()) return ISDF_E_HIP;
   for (int k = 0; k < n_mu; ++k) {
     hipLaunchKernelGGL((qrcp_select<CPLX>), dim3(1), dim3(QR_SEL), 0, s, (const double*)pl.part, nblk, k, n_mu,
                        rtol2, near_tie_rel, nr, (const double*)pl.L, pl.d, pl.lp, pl.st, idx, rdiag, gap, info);
     if (!launch_ok()) return ISDF_E_HIP;
     if (k == n_mu - 1) break;
-    hipLaunchKernelGGL((qrcp_step<TS, CPLX>), dim3(nblk), dim3(QR_TILE), lds_bytes, s, phi, ldp, nphi, psi, lds,
+    hipLaunchKernelGGL((qrcp_step<TS, MODE>), dim3(nblk), dim3(QR_TILE), lds_bytes, s, phi, ldp, nphi, psi, lds,
                        npsi, nr, k, (const QrcpState*)pl.st, pl.L, pl.d, (const double*)pl.lp, pl.part);
     if (!launch_ok()) return ISDF_E_HIP;
   }
@@ -476,21 +502,124 @@ extern "C" int isdf_qrcp(const isdf_grid* grid, isdf_dtype dt, const void* phi, 
   if (n_mu <= 0 || n_mu > nr || nr >= ((int64_t)1 << 31)) return ISDF_E_ARG;
   if (!(rtol >= 0.0 && rtol < 1.0) || !(near_tie_rel >= 0.0)) return ISDF_E_ARG;
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
-  if (qrcp_lds_bytes(n_phi, n_psi, !aliased) > QR_MAX_LDS) return ISDF_E_UNSUPPORTED;
+  if (qrcp_lds_bytes(n_phi, n_psi, aliased ? QR_ALIASED : QR_HADAMARD) > QR_MAX_LDS) return ISDF_E_UNSUPPORTED;
   const QrcpPlan need = plan_qrcp(nullptr, nr, n_mu, !aliased);
   if (!ws || ws_bytes < need.bytes) return ISDF_E_WORKSPACE;
   const QrcpPlan pl = plan_qrcp(ws, nr, n_mu, !aliased);
   hipStream_t s = (hipStream_t)stream;
   if (dt == ISDF_C128) {
     const double *a = (const double*)phi, *b = (const double*)psi;
-    return aliased ? qrcp_run<double, false>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel, idx,
-                                             rdiag, gap, info, pl, s)
-                   : qrcp_run<double, true>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel, idx,
-                                            rdiag, gap, info, pl, s);
+    return aliased ? qrcp_run<double, QR_ALIASED>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel,
+                                                  idx, rdiag, gap, info, pl, s)
+                   : qrcp_run<double, QR_HADAMARD>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel,
+                                                   idx, rdiag, gap, info, pl, s);
   }
   const float *a = (const float*)phi, *b = (const float*)psi;
-  return aliased ? qrcp_run<float, false>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel, idx,
-                                          rdiag, gap, info, pl, s)
-                 : qrcp_run<float, true>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel, idx, rdiag,
-                                         gap, info, pl, s);
+  return aliased ? qrcp_run<float, QR_ALIASED>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel,
+                                               idx, rdiag, gap, info, pl, s)
+                 : qrcp_run<float, QR_HADAMARD>(a, ld_phi, n_phi, b, ld_psi, n_psi, nr, n_mu, rtol, near_tie_rel,
+                                                idx, rdiag, gap, info, pl, s);
+}
+
+namespace isdf {
+namespace {
+
+// R[k][i] = g[i][k] + 0 i (the sketch columns as complex "rows" for the
+// Gram right-hand side), iota[k] = k.
+__global__ void sketch_rows(const double* __restrict__ g, int n, int m, double* __restrict__ R,
+                            int32_t* __restrict__ iota) {
+  const int64_t total = (int64_t)m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / n), i = (int)(e % n);
+    R[2 * e] = g[(int64_t)i * m + k];
+    R[2 * e + 1] = 0.0;
+    if (e < m) iota[e] = (int32_t)e;
+  }
+}
+
+struct SketchPlan {
+  double* X;  // [N_r][m] interleaved complex: Z Omega
+  double *Rphi, *Rpsi, *Ephi, *Epsi;
+  int32_t* iota;
+  int* ab;
+  QrcpPlan q;
+  size_t bytes;
+};
+
+static SketchPlan plan_sketch(void* ws, int64_t nr, int n_mu, int n_phi, int n_psi, int m) {
+  Carver c(ws, (size_t)-1);
+  SketchPlan pl;
+  const int m16 = (int)ceil_div(m, 16) * 16;
+  pl.X = c.take<double>((size_t)nr * 2 * m);
+  pl.Rphi = c.take<double>((size_t)m * 2 * n_phi);
+  pl.Rpsi = c.take<double>((size_t)m * 2 * n_psi);
+  pl.Ephi = c.take<double>((size_t)2 * m16 * 2 * n_phi);
+  pl.Epsi = c.take<double>((size_t)2 * m16 * 2 * n_psi);
+  pl.iota = c.take<int32_t>((size_t)m);
+  pl.ab = c.take<int>(64);
+  const size_t head = c.used;
+  pl.q = plan_qrcp(ws ? (char*)ws + align_up(head, 256) : nullptr, nr, n_mu, true);
+  pl.bytes = align_up(head, 256) + pl.q.bytes;
+  return pl;
+}
+
+template <class TS>
+static int sketch_run(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                      const double* g_phi, const double* g_psi, int m, int64_t nr, int n_mu, double rtol,
+                      double near_tie_rel, int32_t* idx, double* rdiag, double* gap, isdf_qrcp_info* info,
+                      const SketchPlan& pl, hipStream_t s) {
+  const int m16 = (int)ceil_div(m, 16) * 16;
+  if (!fill<int>(pl.ab, 1, 0, s)) return ISDF_E_HIP;
+  // (every entry of iota is written: m <= m n)
+  const unsigned bphi = (unsigned)std::min<int64_t>(ceil_div((int64_t)m * n_phi, 256), 4096);
+  const unsigned bpsi = (unsigned)std::min<int64_t>(ceil_div((int64_t)m * n_psi, 256), 4096);
+  hipLaunchKernelGGL(sketch_rows, dim3(bphi), dim3(256), 0, s, g_phi, n_phi, m, pl.Rphi, pl.iota);
+  hipLaunchKernelGGL(sketch_rows, dim3(bpsi), dim3(256), 0, s, g_psi, n_psi, m, pl.Rpsi, pl.iota);
+  if (!launch_ok()) return ISDF_E_HIP;
+  if (!pack<double, double>(pl.Rphi, n_phi, n_phi, pl.iota, m, m, m16, pl.Ephi, s)) return ISDF_E_HIP;
+  if (!pack<double, double>(pl.Rpsi, n_psi, n_psi, pl.iota, m, m, m16, pl.Epsi, s)) return ISDF_E_HIP;
+  // X = (Phi g_phi) .* conj(Psi g_psi), FP64 (two right-hand sides even when Psi = Phi)
+  SplitWork none{};
+  if (!gram<ISDF_P_FP64, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, false, pl.Ephi, pl.Epsi, m16, m, nullptr, nr, 0,
+                             (int)nr, pl.X, 2 * (int64_t)m, G_CPLX, pl.ab, s, nullptr, &none))
+    return ISDF_E_HIP;
+  return qrcp_run<double, QR_PLAIN>(pl.X, m, m, pl.X, m, m, nr, n_mu, rtol, near_tie_rel, idx, rdiag, gap, info,
+                                    pl.q, s);
+}
+
+}  // namespace
+}  // namespace isdf
+
+extern "C" size_t isdf_qrcp_sketch_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
+                                             int32_t m) {
+  if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || m <= 0) return 0;
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  if (nr <= 0) return 0;
+  return plan_sketch(nullptr, nr, n_mu, n_phi, n_psi, m).bytes;
+}
+
+extern "C" int isdf_qrcp_sketch(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+                                const void* psi, int64_t ld_psi, int32_t n_psi, const double* g_phi,
+                                const double* g_psi, int32_t m, int32_t n_mu, double rtol, double near_tie_rel,
+                                int32_t* idx, double* rdiag, double* gap, isdf_qrcp_info* info, void* ws,
+                                size_t ws_bytes, void* stream) {
+  if (!grid) return ISDF_E_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (grid->n[a] <= 0) return ISDF_E_ARG;
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  if (dt != ISDF_C128 && dt != ISDF_C64) return ISDF_E_ARG;
+  if (!phi || !psi || !g_phi || !g_psi || !idx || !rdiag || !info) return ISDF_E_ARG;
+  if (n_phi <= 0 || n_psi <= 0 || ld_phi < n_phi || ld_psi < n_psi || m <= 0) return ISDF_E_ARG;
+  if (n_mu <= 0 || n_mu > nr || nr >= ((int64_t)1 << 31)) return ISDF_E_ARG;
+  if (!(rtol >= 0.0 && rtol < 1.0) || !(near_tie_rel >= 0.0)) return ISDF_E_ARG;
+  if (qrcp_lds_bytes(m, 0, QR_PLAIN) > QR_MAX_LDS) return ISDF_E_UNSUPPORTED;
+  const SketchPlan need = plan_sketch(nullptr, nr, n_mu, n_phi, n_psi, m);
+  if (!ws || ws_bytes < need.bytes) return ISDF_E_WORKSPACE;
+  const SketchPlan pl = plan_sketch(ws, nr, n_mu, n_phi, n_psi, m);
+  hipStream_t s = (hipStream_t)stream;
+  if (dt == ISDF_C128)
+    return sketch_run<double>((const double*)phi, ld_phi, n_phi, (const double*)psi, ld_psi, n_psi, g_phi, g_psi, m,
+                              nr, n_mu, rtol, near_tie_rel, idx, rdiag, gap, info, pl, s);
+  return sketch_run<float>((const float*)phi, ld_phi, n_phi, (const float*)psi, ld_psi, n_psi, g_phi, g_psi, m, nr,
+                           n_mu, rtol, near_tie_rel, idx, rdiag, gap, info, pl, s);
 }

@@ -203,3 +203,23 @@ def test_saved_gram_entry_points_reject_bad_arguments():
     assert bwd(A=None) == L.E_ARG
     assert bwd(psi=FAKE + 64) == L.E_ARG  # general case needs B
     assert bwd(wsb=saved - 1) == L.E_WORKSPACE
+
+
+def test_qrcp_sketch_rejects_bad_arguments():
+    lib = L.load()
+    g = L.make_grid(8)
+    w = lib.isdf_qrcp_sketch_workspace(C.byref(g), 10, 4, 4, 12)
+    assert w >= 512 * 12 * 16 and lib.isdf_qrcp_sketch_workspace(C.byref(g), 10, 4, 4, 0) == 0
+
+    def call(**over):
+        kw = dict(gp=FAKE, gs=FAKE, m=12, n_mu=10, wsb=1 << 30)
+        kw.update(over)
+        return lib.isdf_qrcp_sketch(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, kw["gp"], kw["gs"], kw["m"],
+                                    kw["n_mu"], 1e-7, 1e-9, FAKE, FAKE, None, FAKE, FAKE, kw["wsb"], None)
+
+    assert call(gp=None) == L.E_ARG
+    assert call(gs=None) == L.E_ARG
+    assert call(m=0) == L.E_ARG
+    assert call(n_mu=600) == L.E_ARG
+    assert call(m=5000) == L.E_UNSUPPORTED
+    assert call(wsb=w - 1) == L.E_WORKSPACE

@@ -138,3 +138,67 @@ def test_qrcp_water64_sampled_properties():
           f"|R_last|/|R_00| {rd[-1] / rd[0]:.3e}, near ties {r.info['near_ties']}")
     assert c["rdiag_rel"] <= 64 * wl.n_mu * EPS
     assert c["greedy_excess"] <= 64 * wl.n_mu * EPS
+
+
+def sketch_inputs(seed, n_phi, n_psi, m):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n_phi, m)), rng.standard_normal((n_psi, m))
+
+
+def test_qrcp_sketch_water8_aliased(water8):
+    """Randomized QRCP on the 8-water box (Psi = Phi), m = N_mu + 8, against
+    the oracle's pivoted QR of the explicit sketch (Z Omega)^T on the same
+    random matrices."""
+    phi = water8["phi"]
+    n_mu = water8["wl"].n_mu
+    gp, gs = sketch_inputs(101, 32, 32, n_mu + 8)
+    o = oracle.qrcp_sketch(phi, phi, n_mu, gp, gs)
+    p = dev(phi)
+    r = isdf.qrcp(p, None, n_mu, grid=water8["wl"].n, sketch=(dev(gp), dev(gs)))
+    kstar = check_against_oracle(phi, phi, r, o, n_mu, greedy_bruteforce=False)
+    if kstar < r.info["rank"]:
+        ex = oracle.qrcp_greedy_excess(phi, phi, r.idx.cpu().numpy()[: r.info["rank"]], gp, gs)
+        assert ex.max() <= 1e-9
+    print(f"water8 sketch: pivots equal up to step {kstar} of {n_mu}")
+
+
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_qrcp_sketch_complex_ragged(dtype):
+    """Psi != Phi, ragged grid, m = 40 sketch rows for 30 pivots; complex64
+    storage against the oracle on the widened values."""
+    phi = synth.random_orthonormal(1430, 7, 21).astype(dtype)
+    psi = synth.random_orthonormal(1430, 9, 22).astype(dtype)
+    gp, gs = sketch_inputs(102, 7, 9, 40)
+    p64, s64 = phi.astype(np.complex128), psi.astype(np.complex128)
+    o = oracle.qrcp_sketch(p64, s64, 30, gp, gs)
+    r = isdf.qrcp(dev(phi), dev(psi), 30, grid=(10, 11, 13), sketch=(dev(gp), dev(gs)))
+    kstar = check_against_oracle(p64, s64, r, o, 30, greedy_bruteforce=False)
+    if kstar < r.info["rank"]:
+        assert oracle.qrcp_greedy_excess(p64, s64, r.idx.cpu().numpy()[: r.info["rank"]], gp, gs).max() <= 1e-9
+
+
+def test_qrcp_sketch_rank_is_capped_by_m():
+    """At most m pivots exist: asking for more returns rank m and -1 after."""
+    phi = synth.random_orthonormal(500, 6, 23)
+    gp, gs = sketch_inputs(103, 6, 6, 12)
+    r = isdf.qrcp(dev(phi), None, 16, rtol=1e-6, sketch=(dev(gp), dev(gs)))
+    assert r.info["rank"] == 12
+    assert (r.idx.cpu().numpy()[12:] == -1).all()
+
+
+def test_qrcp_sketch_orthogonal_kronecker_equals_exact():
+    """Omega = U (x) V with orthogonal U, V (m = N_phi N_psi) keeps every
+    column norm of Z^T: the randomized pivots equal the exact ones."""
+    rng = np.random.default_rng(104)
+    phi = synth.random_orthonormal(800, 3, 24)
+    psi = synth.random_orthonormal(800, 4, 25)
+    u = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+    v = np.linalg.qr(rng.standard_normal((4, 4)))[0]
+    gp = np.repeat(u, 4, axis=1)
+    gs = np.tile(v, (1, 3))
+    ex = isdf.qrcp(dev(phi), dev(psi), 10)
+    sk = isdf.qrcp(dev(phi), dev(psi), 10, sketch=(dev(gp), dev(gs)))
+    o = oracle.qrcp(phi, psi, 10)
+    assert o["gap"].min() > 1e-8
+    assert torch.equal(ex.idx, sk.idx)
+    np.testing.assert_allclose(sk.rdiag.cpu().numpy(), ex.rdiag.cpu().numpy(), rtol=1e-10)
