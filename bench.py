@@ -158,15 +158,15 @@ def poisson_leg(st, wl, steps, exchange=False) -> dict:
     return out
 
 
-def qrcp_leg(phi, psi, wl, km_idx, km_ms, steps) -> dict:
+def qrcp_leg(phi, psi, wl, km_idx, km_ms, steps, sketch_rows=-1) -> dict:
     """Interpolation points by QRCP of Z^T (isdf_qrcp, eq. QRCP), the paper's
     baseline for K-means: HIP-event time of the whole selection, its
     algorithmic HBM bytes (each of the N_mu - 1 column steps reads the
     orbitals and the first k columns of L and writes column k and the
     residual diagonal), and the FP64 fit's least-squares residual at the QRCP
     points beside the K-means points'; then the randomized QRCP of a
-    Khatri-Rao sketch of Z^T with N_mu + 8 rows (isdf_qrcp_sketch), timed and
-    fitted the same way."""
+    Khatri-Rao sketch of Z^T with sketch_rows rows (N_mu + 8 when negative,
+    skipped when 0; isdf_qrcp_sketch), timed and fitted the same way."""
     import math
 
     import numpy as np
@@ -194,23 +194,15 @@ def qrcp_leg(phi, psi, wl, km_idx, km_ms, steps) -> dict:
            "frac": round(nbytes / ms / 1e6 / HBM_PEAK, 4), "rank": r.info["rank"],
            "near_ties": r.info["near_ties"], "r_last_over_r00": float(r.rdiag[-1] / r.rdiag[0]),
            "kmeans_ms": km_ms, "qrcp_over_kmeans_time": round(ms / km_ms, 1) if km_ms else None}
-    # randomized QRCP (Khatri-Rao sketch with m = N_mu + 8 rows, seeded normal)
-    m = wl.n_mu + 8
-    rng = np.random.default_rng(1000 * wl.cfg + 6)
-    gp = torch.as_tensor(rng.standard_normal((wl.n_phi, m))).cuda()
-    gs = torch.as_tensor(rng.standard_normal((wl.n_psi, m))).cuda()
-    api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n, sketch=(gp, gs))
-    torch.cuda.synchronize()
-    a.record()
-    for _ in range(steps):
-        rs = api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n, sketch=(gp, gs))
-    b.record()
-    torch.cuda.synchronize()
-    ms_s = a.elapsed_time(b) / steps
-    out["sketch"] = {"m": m, "ms": round(ms_s, 2), "rank": rs.info["rank"],
-                     "pivots_shared_with_exact": int(np.intersect1d(rs.idx.cpu().numpy(),
-                                                                    r.idx.cpu().numpy()).size)}
-    for name, idx in (("qrcp", r.idx), ("qrcp_sketch", rs.idx), ("kmeans", km_idx)):
+    # randomized QRCP (Khatri-Rao sketch with m rows, seeded normal)
+    m = wl.n_mu + 8 if sketch_rows < 0 else sketch_rows
+    if m == 0:
+        rs = None
+    else:
+        rs = _qrcp_sketch_timed(phi, psi_arg, wl, m, steps, r, out)
+    for name, idx in (("qrcp", r.idx), ("qrcp_sketch", rs.idx if rs is not None else None), ("kmeans", km_idx)):
+        if idx is None:
+            continue
         idx = idx[idx >= 0].contiguous()
         _, minv, info = api.fit(phi, psi_arg, idx, nrows=0)
         res, zz = api.fit_residual(phi, psi_arg, idx, minv, rblock=wl.rblock or None)
@@ -220,6 +212,32 @@ def qrcp_leg(phi, psi, wl, km_idx, km_ms, steps) -> dict:
     torch.cuda.empty_cache()
     log(f"[bench] qrcp: {out}")
     return out
+
+
+def _qrcp_sketch_timed(phi, psi_arg, wl, m, steps, r, out):
+    """Warm-up plus `steps` timed calls of the randomized QRCP with m sketch
+    rows; records the time and the overlap with the exact pivots in out."""
+    import numpy as np
+    import torch
+
+    from paper_2208_07731_amd import api
+
+    rng = np.random.default_rng(1000 * wl.cfg + 6)
+    gp = torch.as_tensor(rng.standard_normal((wl.n_phi, m))).cuda()
+    gs = torch.as_tensor(rng.standard_normal((wl.n_psi, m))).cuda()
+    api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n, sketch=(gp, gs))
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        rs = api.qrcp(phi, psi_arg, wl.n_mu, grid=wl.n, sketch=(gp, gs))
+    b.record()
+    torch.cuda.synchronize()
+    ms_s = a.elapsed_time(b) / steps
+    out["sketch"] = {"m": m, "ms": round(ms_s, 2), "rank": rs.info["rank"],
+                     "pivots_shared_with_exact": int(np.intersect1d(rs.idx.cpu().numpy(),
+                                                                    r.idx.cpu().numpy()).size)}
+    return rs
 
 
 def weight_study(phi, psi, wl, d, kinds) -> dict:
@@ -326,6 +344,8 @@ def main():
                     help="with --poisson: also time the ISDF-compressed exchange (isdf_exchange)")
     ap.add_argument("--qrcp", action="store_true",
                     help="also select the points by QRCP of Z^T (isdf_qrcp) and compare with K-means")
+    ap.add_argument("--qrcp-sketch-rows", type=int, default=-1,
+                    help="with --qrcp: rows m of the randomized QRCP's sketch (default N_mu + 8; 0 skips it)")
     ap.add_argument("--weight-study", default="",
                     help="comma-separated weight functions (ssm,psm,sm,scm,sqm) to compare by fit residuals")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -448,7 +468,8 @@ def main():
     if args.poisson:
         out["poisson"] = poisson_leg(st, wl, args.steps, args.exchange)
     if args.qrcp:
-        out["qrcp"] = qrcp_leg(phi, psi, wl, st.idx.clone(), phases["kmeans"], 1)
+        out["qrcp"] = qrcp_leg(phi, psi, wl, st.idx.clone(), phases["kmeans"], 1,
+                               sketch_rows=args.qrcp_sketch_rows)
     if args.mixed:
         theta64 = st.theta.clone()  # (the last block when streamed)
         del st
