@@ -21,8 +21,16 @@
 // (checked on the hardware).
 //
 // Block-to-tile mapping is XCD aware: workgroups are dispatched round-robin
-// over the 8 XCDs, so consecutive logical tiles (same A row block) are given
-// to workgroups of the same XCD and share its L2.
+// over the 8 XCDs, so consecutive logical tiles are given to workgroups of
+// the same XCD and share its L2; logical tiles run down groups of 8 row
+// blocks, column by column, so the ~64 workgroups resident on one XCD cover
+// about 8 row blocks x 8 column blocks of the output rather than 4 x 16.
+//
+// Each wave raises its issue priority while it issues a pair's MFMAs
+// (s_setprio).  With two waves per SIMD from two workgroups, the raised
+// priority lets one finish its MFMAs first and staggers the two, so that
+// one is less often waiting at its barrier or LDS stores while the other
+// does too (about 3 % on the large FP64 products).
 #pragma once
 
 #include "common.h"
@@ -355,12 +363,14 @@ __device__ __forceinline__ void mma_loop_pp(const Operand<TA>& A, const Operand<
             read2<T, LB, BN, BK>(nbuf + LA_::SIZE, xb + j * 16, 0, 0, lane, fb[nsl][j]);
         }
       }
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
           for (int j = 0; j < Cfg::NI; ++j) MfmaT<T>::mma(fa[sl][i][t], fb[sl][j][t], acc[i][j]);
+      __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_sched_barrier(0);  // keep each pair's MFMAs in place
       if (p == NPAIR - 2 && next) {
         // slice i+1 (in registers since step i-1) into the other buffer, whose
@@ -513,9 +523,12 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh
     while ((int64_t)(tm + 1) * (tm + 2) / 2 <= logical) ++tm;
     while ((int64_t)tm * (tm + 1) / 2 > logical) --tm;
     tn = logical - tm * (tm + 1) / 2;
-  } else {
-    tm = logical / tiles_n;
-    tn = logical % tiles_n;
+  } else {  // groups of GM row blocks, column-major inside a group
+    constexpr int GM = 8;
+    const int g = logical / (GM * tiles_n), r = logical % (GM * tiles_n);
+    const int rows_in = tiles_m - g * GM < GM ? tiles_m - g * GM : GM;  // last group may be short
+    tm = g * GM + r % rows_in;
+    tn = r / rows_in;
   }
   const int m0 = tm * BM, n0 = tn * BN;
   const int batch = blockIdx.y;
