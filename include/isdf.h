@@ -55,6 +55,8 @@ typedef enum {
   ISDF_E_BAD_IDX = 4        /* device: interpolation index out of range or repeated */
 } isdf_status;
 
+/* Entry points take isdf_dtype and isdf_prec values as int32_t; any other
+ * value is rejected with ISDF_E_ARG (workspace queries return 0). */
 typedef enum { ISDF_C128 = 0, ISDF_C64 = 1 } isdf_dtype;
 
 /* Precision of the Gram contractions Phi Phi_mu^H, Psi Psi_mu^H (and of the
@@ -128,7 +130,7 @@ size_t isdf_kmeans_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int
  *   info           device struct, written at the end
  * Deterministic: equal inputs give bitwise equal outputs.
  */
-int isdf_kmeans(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_kmeans(const isdf_grid* grid /* host */, int32_t dt,
                 const void* phi, int64_t ld_phi, int32_t n_phi,
                 const void* psi, int64_t ld_psi, int32_t n_psi,
                 int32_t weight_kind, uint32_t flags, int32_t n_mu,
@@ -157,9 +159,9 @@ size_t isdf_fit_minv_elems(int32_t n_mu, int32_t aliased);
 /* Bytes of workspace for isdf_fit / isdf_fit_backward processing at most
  * `rblock` grid rows at a time.  Host-only. */
 size_t isdf_fit_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi,
-                          int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock);
+                          int32_t n_psi, int32_t aliased, int32_t prec, int64_t rblock);
 size_t isdf_fit_backward_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi,
-                                   int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock);
+                                   int32_t n_psi, int32_t aliased, int32_t prec, int64_t rblock);
 
 /*
  * Interpolation vectors for grid rows [row0, row0 + nrows):
@@ -178,10 +180,10 @@ size_t isdf_fit_backward_workspace(const isdf_grid* grid /* host */, int32_t n_m
  * Rows of Theta are independent given minv: any partition of the grid
  * rows into calls gives the same values.
  */
-int isdf_fit(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_fit(const isdf_grid* grid /* host */, int32_t dt,
              const void* phi, int64_t ld_phi, int32_t n_phi,
              const void* psi, int64_t ld_psi, int32_t n_psi,
-             const int32_t* idx, int32_t n_mu, isdf_prec prec,
+             const int32_t* idx, int32_t n_mu, int32_t prec,
              double* minv, uint32_t flags, int64_t row0, int64_t nrows,
              void* theta, int64_t ld_theta, int64_t rblock,
              isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
@@ -195,12 +197,12 @@ int isdf_fit(const isdf_grid* grid /* host */, isdf_dtype dt,
  * (aliased, ldg >= n_mu) or interleaved complex (ldg >= 2 n_mu doubles).
  * Workspace: isdf_zc_workspace bytes for calls of up to `nrows` rows.
  */
-size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec,
+size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, int32_t prec,
                          int64_t nrows);
-int isdf_zc(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_zc(const isdf_grid* grid /* host */, int32_t dt,
             const void* phi, int64_t ld_phi, int32_t n_phi,
             const void* psi, int64_t ld_psi, int32_t n_psi,
-            const int32_t* idx, int32_t n_mu, isdf_prec prec,
+            const int32_t* idx, int32_t n_mu, int32_t prec,
             int64_t row0, int64_t nrows, double* G, int64_t ldg,
             void* ws, size_t ws_bytes, void* stream);
 
@@ -212,10 +214,10 @@ int isdf_zc(const isdf_grid* grid /* host */, isdf_dtype dt,
  * isdf_fit_backward_gram.  Same workspace as isdf_zc.  B is unused (may be
  * NULL) in the aliased case.
  */
-int isdf_zc_ab(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_zc_ab(const isdf_grid* grid /* host */, int32_t dt,
                const void* phi, int64_t ld_phi, int32_t n_phi,
                const void* psi, int64_t ld_psi, int32_t n_psi,
-               const int32_t* idx, int32_t n_mu, isdf_prec prec,
+               const int32_t* idx, int32_t n_mu, int32_t prec,
                int64_t row0, int64_t nrows, double* G, int64_t ldg, double* A, double* B,
                void* ws, size_t ws_bytes, void* stream);
 
@@ -227,7 +229,7 @@ int isdf_zc_ab(const isdf_grid* grid /* host */, isdf_dtype dt,
  * launch; no workspace.
  */
 int isdf_apply_minv(int32_t n_mu, int32_t aliased, const double* minv, const double* G, int64_t ldg,
-                    int64_t nrows, isdf_dtype dt, void* theta, int64_t ld_theta, void* stream);
+                    int64_t nrows, int32_t dt, void* theta, int64_t ld_theta, void* stream);
 
 /*
  * Adjoint of isdf_fit with the interpolation points fixed (the paper gives
@@ -249,10 +251,10 @@ int isdf_apply_minv(int32_t n_mu, int32_t aliased, const double* minv, const dou
  *   rblock     grid rows per internal step; Theta is recomputed per block,
  *              never stored whole
  */
-int isdf_fit_backward(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_fit_backward(const isdf_grid* grid /* host */, int32_t dt,
                       const void* phi, int64_t ld_phi, int32_t n_phi,
                       const void* psi, int64_t ld_psi, int32_t n_psi,
-                      const int32_t* idx, int32_t n_mu, isdf_prec prec,
+                      const int32_t* idx, int32_t n_mu, int32_t prec,
                       const double* minv,
                       const void* theta_bar, int64_t ld_tbar, const double* g,
                       void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi,
@@ -272,11 +274,11 @@ int isdf_fit_backward(const isdf_grid* grid /* host */, isdf_dtype dt,
  * Gram product per call.
  */
 size_t isdf_fit_backward_gram_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi,
-                                        int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock);
-int isdf_fit_backward_gram(const isdf_grid* grid /* host */, isdf_dtype dt,
+                                        int32_t n_psi, int32_t aliased, int32_t prec, int64_t rblock);
+int isdf_fit_backward_gram(const isdf_grid* grid /* host */, int32_t dt,
                            const void* phi, int64_t ld_phi, int32_t n_phi,
                            const void* psi, int64_t ld_psi, int32_t n_psi,
-                           const int32_t* idx, int32_t n_mu, isdf_prec prec,
+                           const int32_t* idx, int32_t n_mu, int32_t prec,
                            const double* minv,
                            const void* theta_bar, int64_t ld_tbar, const double* g,
                            void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi,
@@ -296,11 +298,11 @@ int isdf_fit_backward_gram(const isdf_grid* grid /* host */, isdf_dtype dt,
  * bytes.  Sums are in a fixed order (reproducible bit for bit).
  */
 size_t isdf_fit_residual_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi, int32_t n_psi,
-                                   int32_t aliased, isdf_prec prec, int64_t rblock);
-int isdf_fit_residual(const isdf_grid* grid /* host */, isdf_dtype dt,
+                                   int32_t aliased, int32_t prec, int64_t rblock);
+int isdf_fit_residual(const isdf_grid* grid /* host */, int32_t dt,
                       const void* phi, int64_t ld_phi, int32_t n_phi,
                       const void* psi, int64_t ld_psi, int32_t n_psi,
-                      const int32_t* idx, int32_t n_mu, isdf_prec prec,
+                      const int32_t* idx, int32_t n_mu, int32_t prec,
                       const double* minv, int64_t rblock, double* out,
                       isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
 
@@ -317,7 +319,7 @@ int isdf_fit_residual(const isdf_grid* grid /* host */, isdf_dtype dt,
  * a fixed order.
  */
 size_t isdf_cluster_residual_workspace(void);
-int isdf_cluster_residual(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_cluster_residual(const isdf_grid* grid /* host */, int32_t dt,
                           const void* phi, int64_t ld_phi, int32_t n_phi,
                           const void* psi, int64_t ld_psi, int32_t n_psi,
                           const int32_t* labels, const int32_t* idx, int32_t n_mu, double* out,
@@ -338,7 +340,7 @@ int isdf_cluster_residual(const isdf_grid* grid /* host */, isdf_dtype dt,
  * isdf_poisson_workspace bytes (0 for an unsupported grid).
  */
 size_t isdf_poisson_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t is_complex);
-int isdf_poisson(const isdf_grid* grid /* host */, isdf_dtype dt, const void* theta, int64_t ld_theta,
+int isdf_poisson(const isdf_grid* grid /* host */, int32_t dt, const void* theta, int64_t ld_theta,
                  int32_t n_mu, int32_t is_complex, void* V, int64_t ld_v, void* ws, size_t ws_bytes,
                  void* stream);
 
@@ -359,7 +361,7 @@ int isdf_poisson(const isdf_grid* grid /* host */, isdf_dtype dt, const void* th
  */
 size_t isdf_exchange_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi, int32_t n_psi,
                                int64_t rblock);
-int isdf_exchange(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_exchange(const isdf_grid* grid /* host */, int32_t dt,
                   const void* phi, int64_t ld_phi, int32_t n_phi,
                   const void* psi, int64_t ld_psi, int32_t n_psi,
                   const int32_t* idx, int32_t n_mu, const void* V, int64_t ld_v, int32_t v_complex,
@@ -409,7 +411,7 @@ size_t isdf_qrcp_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32
  * (N_phi + N_psi above about 3000).  Deterministic: equal inputs give
  * bitwise equal outputs.
  */
-int isdf_qrcp(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_qrcp(const isdf_grid* grid /* host */, int32_t dt,
               const void* phi, int64_t ld_phi, int32_t n_phi,
               const void* psi, int64_t ld_psi, int32_t n_psi,
               int32_t n_mu, double rtol, double near_tie_rel,
@@ -436,7 +438,7 @@ int isdf_qrcp(const isdf_grid* grid /* host */, isdf_dtype dt,
  */
 size_t isdf_qrcp_sketch_workspace(const isdf_grid* grid /* host */, int32_t n_mu, int32_t n_phi, int32_t n_psi,
                                   int32_t m);
-int isdf_qrcp_sketch(const isdf_grid* grid /* host */, isdf_dtype dt,
+int isdf_qrcp_sketch(const isdf_grid* grid /* host */, int32_t dt,
                      const void* phi, int64_t ld_phi, int32_t n_phi,
                      const void* psi, int64_t ld_psi, int32_t n_psi,
                      const double* g_phi, const double* g_psi, int32_t m,

@@ -5,6 +5,12 @@
 Every .hip file is compiled to an object under _build/ (in parallel), then
 linked into paper_2208_07731_amd/libisdf.so.  hipcc cross-compiles, so this
 runs on a machine without a GPU.
+
+build_host_sanitized() makes a second copy under _build/host_sanitized/
+whose host code is instrumented with AddressSanitizer and
+UndefinedBehaviorSanitizer (device code is compiled as usual).  It is for
+CPU-side checks of the C ABI's argument handling; the tests load it with the
+sanitizer runtime preloaded.
 """
 from __future__ import annotations
 
@@ -31,9 +37,15 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+# host-only instrumentation: every -fsanitize= goes to the host pass
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer"]
+SAN_DIR = os.path.join(BUILD, "host_sanitized")
+
+
+def _compile(src: str, verbose: bool, out_dir: str = BUILD, extra: tuple = ()) -> str:
+    obj = os.path.join(out_dir, os.path.basename(src)[:-4] + ".o")
+    cmd = [HIPCC, *CFLAGS, *extra, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,6 +72,43 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
     return LIB
+
+
+def sanitizer_runtime() -> str | None:
+    """Path of the AddressSanitizer runtime that hipcc's host compiler links
+    against (to be preloaded into the process that loads the instrumented
+    library), or None."""
+    r = subprocess.run([HIPCC, "--print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path):
+        return path
+    import glob
+
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """libisdf.so with ASan + UBSan host code under _build/host_sanitized/;
+    rebuilt only when a source is newer than the library."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    lib = os.path.join(SAN_DIR, "libisdf.so")
+    srcs = sources()
+    deps = srcs + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps.append(os.path.join(os.path.dirname(HERE), "include", "isdf.h"))
+    if os.path.exists(lib) and os.path.getmtime(lib) >= max(os.path.getmtime(d) for d in deps):
+        return lib
+    extra = ("-O1", "-g", *HOST_SAN)
+    with cf.ThreadPoolExecutor(min(len(srcs), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose, SAN_DIR, extra), srcs))
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *HOST_SAN, "-shared-libsan", *objs, "-o", tmp,
+           "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

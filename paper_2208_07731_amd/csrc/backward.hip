@@ -624,33 +624,45 @@ static int bwd_dispatch(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
 using namespace isdf;
 
 extern "C" size_t isdf_fit_backward_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
-                                              int32_t aliased, isdf_prec prec, int64_t rblock) {
+                                              int32_t aliased, int32_t prec_in, int64_t rblock) {
+  if (!prec_valid(prec_in)) return 0;
+  const isdf_prec prec = (isdf_prec)prec_in;
   return bwd_workspace(grid, n_mu, n_phi, n_psi, aliased, prec, rblock, false);
 }
 
-extern "C" int isdf_fit_backward(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+extern "C" int isdf_fit_backward(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
                                  int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx,
-                                 int32_t n_mu, isdf_prec prec, const double* minv, const void* theta_bar,
+                                 int32_t n_mu, int32_t prec_in, const double* minv, const void* theta_bar,
                                  int64_t ld_tbar, const double* g, void* dphi, int64_t ld_dphi, void* dpsi,
                                  int64_t ld_dpsi, double* loss, int64_t rblock, isdf_fit_info* info, void* ws,
                                  size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  if (!prec_valid(prec_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
+  const isdf_prec prec = (isdf_prec)prec_in;
   return bwd_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, minv, theta_bar, ld_tbar, g,
                       dphi, ld_dphi, dpsi, ld_dpsi, loss, rblock, nullptr, nullptr, nullptr, false, info, ws, ws_bytes,
                       stream);
 }
 
 extern "C" size_t isdf_fit_backward_gram_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi,
-                                                   int32_t n_psi, int32_t aliased, isdf_prec prec, int64_t rblock) {
+                                                   int32_t n_psi, int32_t aliased, int32_t prec_in, int64_t rblock) {
+  if (!prec_valid(prec_in)) return 0;
+  const isdf_prec prec = (isdf_prec)prec_in;
   return bwd_workspace(grid, n_mu, n_phi, n_psi, aliased, prec, rblock, true);
 }
 
-extern "C" int isdf_fit_backward_gram(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+extern "C" int isdf_fit_backward_gram(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
                                       int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
-                                      const int32_t* idx, int32_t n_mu, isdf_prec prec, const double* minv,
+                                      const int32_t* idx, int32_t n_mu, int32_t prec_in, const double* minv,
                                       const void* theta_bar, int64_t ld_tbar, const double* g, void* dphi,
                                       int64_t ld_dphi, void* dpsi, int64_t ld_dpsi, double* loss, int64_t rblock,
                                       double* G, double* A, double* B, isdf_fit_info* info, void* ws,
                                       size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  if (!prec_valid(prec_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
+  const isdf_prec prec = (isdf_prec)prec_in;
   return bwd_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, minv, theta_bar, ld_tbar, g,
                       dphi, ld_dphi, dpsi, ld_dpsi, loss, rblock, G, A, B, true, info, ws, ws_bytes, stream);
 }

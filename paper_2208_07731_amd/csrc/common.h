@@ -21,6 +21,12 @@
     if (s_ != ISDF_OK) return s_;                 \
   } while (0)
 
+// Entry points take the enumerations as int32_t and check them before any
+// conversion: a value outside an enumeration's range is undefined behaviour
+// once loaded as the enum type.
+static inline bool dtype_valid(int32_t v) { return v == ISDF_C128 || v == ISDF_C64; }
+static inline bool prec_valid(int32_t v) { return v >= ISDF_P_FP64 && v <= ISDF_P_FP16X3; }
+
 namespace isdf {
 
 static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

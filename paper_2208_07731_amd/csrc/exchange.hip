@@ -99,10 +99,12 @@ extern "C" size_t isdf_exchange_workspace(const isdf_grid* grid, int32_t n_mu, i
   return plan_exch(nullptr, 0, n_mu, n_phi, n_psi, rblock).bytes;
 }
 
-extern "C" int isdf_exchange(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+extern "C" int isdf_exchange(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi, int32_t n_phi,
                              const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
                              const void* V, int64_t ld_v, int32_t v_complex, void* W, int64_t ld_w, int64_t rblock,
                              void* ws, size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
   int64_t nr = 0;
   if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, ISDF_P_FP64, &nr)) return ISDF_E_ARG;
   if (!V || !W || ld_v < n_mu || ld_w < n_psi || rblock <= 0) return ISDF_E_ARG;

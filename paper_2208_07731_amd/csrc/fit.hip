@@ -188,7 +188,9 @@ static int resid_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const
 using namespace isdf;
 
 extern "C" size_t isdf_fit_residual_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
-                                              int32_t aliased, isdf_prec prec, int64_t rblock) {
+                                              int32_t aliased, int32_t prec_in, int64_t rblock) {
+  if (!prec_valid(prec_in)) return 0;
+  const isdf_prec prec = (isdf_prec)prec_in;
   if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
   const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   if (nr <= 0) return 0;
@@ -196,10 +198,14 @@ extern "C" size_t isdf_fit_residual_workspace(const isdf_grid* grid, int32_t n_m
   return plan_fit(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, prec, rblock, true).bytes;
 }
 
-extern "C" int isdf_fit_residual(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+extern "C" int isdf_fit_residual(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
                                  int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx,
-                                 int32_t n_mu, isdf_prec prec, const double* minv, int64_t rblock, double* out,
+                                 int32_t n_mu, int32_t prec_in, const double* minv, int64_t rblock, double* out,
                                  isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  if (!prec_valid(prec_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
+  const isdf_prec prec = (isdf_prec)prec_in;
   int64_t nr = 0;
   if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
   if (!minv || !out || !info || rblock <= 0) return ISDF_E_ARG;
@@ -235,18 +241,24 @@ extern "C" size_t isdf_fit_minv_elems(int32_t n_mu, int32_t aliased) {
 }
 
 extern "C" size_t isdf_fit_workspace(const isdf_grid* grid, int32_t n_mu, int32_t n_phi, int32_t n_psi,
-                                     int32_t aliased, isdf_prec prec, int64_t rblock) {
+                                     int32_t aliased, int32_t prec_in, int64_t rblock) {
+  if (!prec_valid(prec_in)) return 0;
+  const isdf_prec prec = (isdf_prec)prec_in;
   if (!grid || n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || rblock <= 0) return 0;
   const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   if (nr <= 0) return 0;
   return plan_fit(nullptr, 0, nr, n_mu, n_phi, n_psi, aliased != 0, prec, rblock).bytes;
 }
 
-extern "C" int isdf_fit(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+extern "C" int isdf_fit(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi, int32_t n_phi,
                         const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
-                        isdf_prec prec, double* minv, uint32_t flags, int64_t row0, int64_t nrows, void* theta,
+                        int32_t prec_in, double* minv, uint32_t flags, int64_t row0, int64_t nrows, void* theta,
                         int64_t ld_theta, int64_t rblock, isdf_fit_info* info, void* ws, size_t ws_bytes,
                         void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  if (!prec_valid(prec_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
+  const isdf_prec prec = (isdf_prec)prec_in;
   int64_t nr = 0;
   if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
   if (flags & ~ISDF_FIT_FACTOR) return ISDF_E_ARG;
@@ -302,8 +314,10 @@ static ZcPlan plan_zc(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bool
   return P;
 }
 
-extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, isdf_prec prec,
+extern "C" size_t isdf_zc_workspace(int32_t n_mu, int32_t n_phi, int32_t n_psi, int32_t aliased, int32_t prec_in,
                                     int64_t nrows) {
+  if (!prec_valid(prec_in)) return 0;
+  const isdf_prec prec = (isdf_prec)prec_in;
   if (n_mu <= 0 || n_phi <= 0 || n_psi <= 0 || nrows < 0) return 0;
   return plan_zc(nullptr, 0, n_mu, n_phi, n_psi, aliased != 0, prec, nrows).bytes;
 }
@@ -362,24 +376,34 @@ static int zc_dispatch(const isdf_grid* grid, isdf_dtype dt, const void* phi, in
 #undef ISDF_ZC_ARGS
 }
 
-extern "C" int isdf_zc(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+extern "C" int isdf_zc(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi, int32_t n_phi,
                        const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
-                       isdf_prec prec, int64_t row0, int64_t nrows, double* G, int64_t ldg, void* ws,
+                       int32_t prec_in, int64_t row0, int64_t nrows, double* G, int64_t ldg, void* ws,
                        size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  if (!prec_valid(prec_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
+  const isdf_prec prec = (isdf_prec)prec_in;
   return zc_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, row0, nrows, G, ldg, nullptr,
                      nullptr, false, ws, ws_bytes, stream);
 }
 
-extern "C" int isdf_zc_ab(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+extern "C" int isdf_zc_ab(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi, int32_t n_phi,
                           const void* psi, int64_t ld_psi, int32_t n_psi, const int32_t* idx, int32_t n_mu,
-                          isdf_prec prec, int64_t row0, int64_t nrows, double* G, int64_t ldg, double* A, double* B,
+                          int32_t prec_in, int64_t row0, int64_t nrows, double* G, int64_t ldg, double* A, double* B,
                           void* ws, size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  if (!prec_valid(prec_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
+  const isdf_prec prec = (isdf_prec)prec_in;
   return zc_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, row0, nrows, G, ldg, A, B,
                      true, ws, ws_bytes, stream);
 }
 
 extern "C" int isdf_apply_minv(int32_t n_mu, int32_t aliased, const double* minv, const double* G, int64_t ldg,
-                               int64_t nrows, isdf_dtype dt, void* theta, int64_t ld_theta, void* stream) {
+                               int64_t nrows, int32_t dt_in, void* theta, int64_t ld_theta, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
   const int64_t n1 = aliased ? n_mu : 2 * (int64_t)n_mu;
   if (n_mu <= 0 || !minv || nrows < 0 || nrows > INT32_MAX || (nrows > 0 && (!G || !theta))) return ISDF_E_ARG;
   if (ldg < n1 || ld_theta < n_mu || (dt != ISDF_C128 && dt != ISDF_C64)) return ISDF_E_ARG;

@@ -533,12 +533,14 @@ extern "C" size_t isdf_kmeans_workspace(const isdf_grid* grid, int32_t n_mu, int
   return plan_kmeans(nullptr, 0, nr, n_mu, max_iter, assign_blocks(G), true, true, true, true).bytes;
 }
 
-extern "C" int isdf_kmeans(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+extern "C" int isdf_kmeans(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
                            int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
                            int32_t weight_kind, uint32_t flags, int32_t n_mu, const double* c0,
                            int32_t max_iter, double near_tie_rel, int32_t* idx, double* centroids,
                            int32_t* labels, double* w, double* objective, isdf_kmeans_info* info,
                            void* ws, size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
   if (!grid_ok(grid)) return ISDF_E_ARG;
   const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   const bool wgiven = (flags & ISDF_KM_WEIGHT_GIVEN) != 0;

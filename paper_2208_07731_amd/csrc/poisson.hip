@@ -416,8 +416,10 @@ extern "C" size_t isdf_poisson_workspace(const isdf_grid* grid, int32_t n_mu, in
   return plan_poisson(nullptr, 0, nr, n_mu, is_complex != 0, plan.ntw).bytes;
 }
 
-extern "C" int isdf_poisson(const isdf_grid* grid, isdf_dtype dt, const void* theta, int64_t ld_theta, int32_t n_mu,
+extern "C" int isdf_poisson(const isdf_grid* grid, int32_t dt_in, const void* theta, int64_t ld_theta, int32_t n_mu,
                             int32_t is_complex, void* V, int64_t ld_v, void* ws, size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
   if (!grid || !theta || !V || n_mu <= 0 || ld_theta < n_mu || ld_v < n_mu) return ISDF_E_ARG;
   if (dt != ISDF_C128 && dt != ISDF_C64) return ISDF_E_ARG;
   for (int a = 0; a < 3; ++a)

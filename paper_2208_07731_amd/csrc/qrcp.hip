@@ -488,10 +488,12 @@ extern "C" size_t isdf_qrcp_workspace(const isdf_grid* grid, int32_t n_mu, int32
   return plan_qrcp(nullptr, nr, n_mu, !aliased).bytes;
 }
 
-extern "C" int isdf_qrcp(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+extern "C" int isdf_qrcp(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi, int32_t n_phi,
                          const void* psi, int64_t ld_psi, int32_t n_psi, int32_t n_mu, double rtol,
                          double near_tie_rel, int32_t* idx, double* rdiag, double* gap, isdf_qrcp_info* info,
                          void* ws, size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
   if (!grid) return ISDF_E_ARG;
   for (int a = 0; a < 3; ++a)
     if (grid->n[a] <= 0) return ISDF_E_ARG;
@@ -598,11 +600,13 @@ extern "C" size_t isdf_qrcp_sketch_workspace(const isdf_grid* grid, int32_t n_mu
   return plan_sketch(nullptr, nr, n_mu, n_phi, n_psi, m).bytes;
 }
 
-extern "C" int isdf_qrcp_sketch(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+extern "C" int isdf_qrcp_sketch(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi, int32_t n_phi,
                                 const void* psi, int64_t ld_psi, int32_t n_psi, const double* g_phi,
                                 const double* g_psi, int32_t m, int32_t n_mu, double rtol, double near_tie_rel,
                                 int32_t* idx, double* rdiag, double* gap, isdf_qrcp_info* info, void* ws,
                                 size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
   if (!grid) return ISDF_E_ARG;
   for (int a = 0; a < 3; ++a)
     if (grid->n[a] <= 0) return ISDF_E_ARG;

@@ -71,10 +71,12 @@ using namespace isdf;
 
 extern "C" size_t isdf_cluster_residual_workspace(void) { return (size_t)2 * RES_BLOCKS * sizeof(double); }
 
-extern "C" int isdf_cluster_residual(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi,
+extern "C" int isdf_cluster_residual(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
                                      int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
                                      const int32_t* labels, const int32_t* idx, int32_t n_mu, double* out, void* ws,
                                      size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
   if (!grid) return ISDF_E_ARG;
   for (int a = 0; a < 3; ++a)
     if (grid->n[a] <= 0) return ISDF_E_ARG;

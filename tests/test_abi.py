@@ -223,3 +223,38 @@ def test_qrcp_sketch_rejects_bad_arguments():
     assert call(n_mu=600) == L.E_ARG
     assert call(m=5000) == L.E_UNSUPPORTED
     assert call(wsb=w - 1) == L.E_WORKSPACE
+
+
+@pytest.mark.parametrize("bad", [-1, 2, 7, 1 << 20])
+def test_out_of_range_enumerations_are_rejected(bad):
+    """dtype and precision arrive as int32; values outside isdf_dtype /
+    isdf_prec are rejected on the host (workspace queries return 0)."""
+    lib = L.load()
+    g = L.make_grid(8)
+    badp = bad + 2 if bad == 2 else bad  # 2 is a valid precision (BF16x6)
+    assert lib.isdf_fit_workspace(C.byref(g), 5, 4, 4, 1, badp, 512) == 0
+    assert lib.isdf_fit_residual_workspace(C.byref(g), 5, 4, 4, 1, badp, 512) == 0
+    assert lib.isdf_zc_workspace(5, 4, 4, 1, badp, 512) == 0
+    assert lib.isdf_fit_backward_workspace(C.byref(g), 5, 4, 4, 1, badp, 512) == 0
+    assert lib.isdf_fit_backward_gram_workspace(C.byref(g), 5, 4, 4, 1, badp, 512) == 0
+    for dt, prec in ((bad, 0), (L.C128, badp)):
+        assert lib.isdf_fit(C.byref(g), dt, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, prec, FAKE, 1, 0, 512, FAKE, 5, 512,
+                            FAKE, FAKE, 1 << 30, None) == L.E_ARG
+        assert lib.isdf_zc(C.byref(g), dt, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, prec, 0, 512, FAKE, 5, FAKE, 1 << 30,
+                           None) == L.E_ARG
+        assert lib.isdf_fit_backward(C.byref(g), dt, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, prec, FAKE, None, 0, FAKE,
+                                     FAKE, 4, FAKE + 4096, 4, None, 512, FAKE, FAKE, 1 << 30, None) == L.E_ARG
+        assert lib.isdf_fit_residual(C.byref(g), dt, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, prec, FAKE, 512, FAKE, FAKE,
+                                     FAKE, 1 << 30, None) == L.E_ARG
+    assert lib.isdf_kmeans(C.byref(g), bad, FAKE, 4, 4, FAKE, 4, 4, 0, 0, 5, FAKE, 3, 1e-6, FAKE, None, None, None,
+                           None, FAKE, FAKE, 1 << 30, None) == L.E_ARG
+    assert lib.isdf_apply_minv(5, 1, FAKE, FAKE, 5, 512, bad, FAKE, 5, None) == L.E_ARG
+    assert lib.isdf_poisson(C.byref(g), bad, FAKE, 10, 10, 0, FAKE, 10, FAKE, 1 << 30, None) == L.E_ARG
+    assert lib.isdf_exchange(C.byref(g), bad, FAKE, 4, 4, FAKE, 4, 4, FAKE, 5, FAKE, 5, 0, FAKE, 4, 512, FAKE,
+                             1 << 30, None) == L.E_ARG
+    assert lib.isdf_qrcp(C.byref(g), bad, FAKE, 4, 4, FAKE, 4, 4, 10, 1e-7, 1e-9, FAKE, FAKE, None, FAKE, FAKE,
+                         1 << 30, None) == L.E_ARG
+    assert lib.isdf_qrcp_sketch(C.byref(g), bad, FAKE, 4, 4, FAKE, 4, 4, FAKE, FAKE, 12, 10, 1e-7, 1e-9, FAKE, FAKE,
+                                None, FAKE, FAKE, 1 << 30, None) == L.E_ARG
+    assert lib.isdf_cluster_residual(C.byref(g), bad, FAKE, 4, 4, FAKE, 4, 4, FAKE, FAKE, 5, FAKE, FAKE, 1 << 20,
+                                     None) == L.E_ARG
