@@ -429,8 +429,8 @@ int isdf_qrcp(const isdf_grid* grid /* host */, int32_t dt,
  * isdf_qrcp.
  *   g_phi [n_phi][m], g_psi [n_psi][m]  FP64 device: the random numbers
  *        (the caller draws them, e.g. standard normal)
- *   m    sketch size, 1 <= m <= 3072; at most m pivots exist, so m >= n_mu
- *        for a full set
+ *   m    sketch size, m >= 1; at most m pivots exist, so m >= n_mu for a
+ *        full set
  *   other arguments and outputs as isdf_qrcp.
  * Cost: 8 N_r m (N_phi + N_psi) flops for X, then n_mu passes over X and
  * over L: more than isdf_qrcp whenever m > (N_phi + N_psi) / 2.  Workspace:

@@ -174,8 +174,9 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi,
   constexpr bool CPLX = MODE != QR_ALIASED;
   constexpr bool TWO = MODE == QR_HADAMARD;  // a second orbital set
   constexpr int CW = CPLX ? 2 : 1;
+  constexpr bool STAGE = MODE != QR_PLAIN;  // copy the pivot's orbital rows to LDS
   double2* sphi = reinterpret_cast<double2*>(lds_mem);
-  double2* spsi = sphi + nphi;
+  double2* spsi = sphi + (STAGE ? nphi : 0);
   double* slp = reinterpret_cast<double*>(spsi + (TWO ? npsi : 0));
   const int64_t p = st->p;
   const double dp = st->dp;
@@ -183,10 +184,19 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi,
   const int lane = tid & (ISDF_WAVE - 1);
   const int wv = tid / ISDF_WAVE;
 
-  for (int i = tid; i < nphi; i += QR_TILE) sphi[i] = Cplx<TS>::load(phi + 2 * (p * ldp + i));
+  if (STAGE)
+    for (int i = tid; i < nphi; i += QR_TILE) sphi[i] = Cplx<TS>::load(phi + 2 * (p * ldp + i));
   if (TWO)
     for (int i = tid; i < npsi; i += QR_TILE) spsi[i] = Cplx<TS>::load(psi + 2 * (p * lds + i));
   __syncthreads();
+  // the sketch's pivot row (m complex FP64 values, possibly more than LDS
+  // holds) is read in place: every wavefront reads the same row, which
+  // stays in the caches
+  const double2* __restrict__ qphi;
+  if constexpr (STAGE)
+    qphi = sphi;
+  else
+    qphi = reinterpret_cast<const double2*>(phi) + p * ldp;
 
   // ---- phase 1: c = K(r, p): a conj(b), |a|^2 or a, a = Phi(r).conj(Phi(p)), b likewise
   const int64_t base = (int64_t)blockIdx.x * QR_TILE + wv * ISDF_WAVE;
@@ -200,7 +210,7 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_step(const TS* __restrict__ phi,
       if (r < nr) {
         for (int i = lane; i < nphi; i += ISDF_WAVE) {
           const double2 z = Cplx<TS>::load(phi + 2 * (r * ldp + i));
-          const double2 q = sphi[i];
+          const double2 q = qphi[i];
           ar[u] += z.x * q.x + z.y * q.y;
           ai[u] += z.y * q.x - z.x * q.y;
         }
@@ -422,7 +432,7 @@ __global__ void qrcp_reset(QrcpState* st) {
 
 // LDS of one qrcp_step workgroup: Phi(p), Psi(p) and a chunk of the pivot's row of L.
 static size_t qrcp_lds_bytes(int n_phi, int n_psi, int mode) {
-  return sizeof(double2) * (size_t)(n_phi + (mode == QR_HADAMARD ? n_psi : 0)) +
+  return sizeof(double2) * (size_t)((mode == QR_PLAIN ? 0 : n_phi) + (mode == QR_HADAMARD ? n_psi : 0)) +
          sizeof(double) * QR_LPC * (mode == QR_ALIASED ? 1 : 2);
 }
 static constexpr size_t QR_MAX_LDS = 64 * 1024;
@@ -616,7 +626,6 @@ extern "C" int isdf_qrcp_sketch(const isdf_grid* grid, int32_t dt_in, const void
   if (n_phi <= 0 || n_psi <= 0 || ld_phi < n_phi || ld_psi < n_psi || m <= 0) return ISDF_E_ARG;
   if (n_mu <= 0 || n_mu > nr || nr >= ((int64_t)1 << 31)) return ISDF_E_ARG;
   if (!(rtol >= 0.0 && rtol < 1.0) || !(near_tie_rel >= 0.0)) return ISDF_E_ARG;
-  if (qrcp_lds_bytes(m, 0, QR_PLAIN) > QR_MAX_LDS) return ISDF_E_UNSUPPORTED;
   const SketchPlan need = plan_sketch(nullptr, nr, n_mu, n_phi, n_psi, m);
   if (!ws || ws_bytes < need.bytes) return ISDF_E_WORKSPACE;
   const SketchPlan pl = plan_sketch(ws, nr, n_mu, n_phi, n_psi, m);

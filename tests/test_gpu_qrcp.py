@@ -202,3 +202,17 @@ def test_qrcp_sketch_orthogonal_kronecker_equals_exact():
     assert o["gap"].min() > 1e-8
     assert torch.equal(ex.idx, sk.idx)
     np.testing.assert_allclose(sk.rdiag.cpu().numpy(), ex.rdiag.cpu().numpy(), rtol=1e-10)
+
+
+def test_qrcp_sketch_wider_than_lds():
+    """m = 3500 sketch columns: the pivot's sketch row (56 KB) is read in
+    place rather than staged in LDS, so m has no upper limit; Psi != Phi on
+    a 12^3 grid, 30 pivots, against the oracle on the explicit sketch."""
+    phi = synth.random_orthonormal(1728, 6, 31)
+    psi = synth.random_orthonormal(1728, 7, 32)
+    gp, gs = sketch_inputs(105, 6, 7, 3500)
+    o = oracle.qrcp_sketch(phi, psi, 30, gp, gs)
+    r = isdf.qrcp(dev(phi), dev(psi), 30, grid=(12, 12, 12), sketch=(dev(gp), dev(gs)))
+    kstar = check_against_oracle(phi, psi, r, o, 30, greedy_bruteforce=False)
+    if kstar < r.info["rank"]:
+        assert oracle.qrcp_greedy_excess(phi, psi, r.idx.cpu().numpy()[: r.info["rank"]], gp, gs).max() <= 1e-9
