@@ -160,7 +160,8 @@ __global__ __launch_bounds__(QR_TILE) void qrcp_init(const TS* __restrict__ phi,
 }
 
 // One column of L.  Phase 1: one wavefront per row for K(r, p) (lanes over
-// the orbitals, Phi(p) and Psi(p) from LDS).  Phase 2: one thread per row
+// the orbitals, Phi(p) and Psi(p) from LDS; the sketch's row X(p) in place).
+// Phase 2: one thread per row
 // for the projection on the earlier columns (column-major L, coalesced; the
 // pivot's row of L broadcast from LDS in chunks).
 template <class TS, int MODE>
