@@ -53,7 +53,7 @@ struct KmGeom {
   int aniso;
 };
 
-constexpr int ASSIGN_THREADS = 256;  // 4 wavefronts = 4 bricks
+constexpr int ASSIGN_THREADS = 512;  // 8 wavefronts = 8 bricks
 constexpr int CTILE = 2048;          // centroids staged per LDS tile
 
 // Squared distance with the same operation order as the definition
