@@ -331,27 +331,55 @@ __device__ double reduce_jpart(const double* __restrict__ jp, int n, int lane) {
 }
 
 // Walks the bounding box of cluster `mu` line by line (lines along the last
-// axis); calls f(p, i, j, k) for every grid point of the box, each lane a
-// fixed subset in a fixed order.
-template <class F>
-__device__ __forceinline__ void scan_bbox(const int* b, const KmGeom& g, int lane, F&& f) {
+// axis); each lane visits a fixed subset of the box's grid points in a fixed
+// order.  The points are taken SCAN_U at a time: load(p) for all of them
+// first (independent loads, in flight together), then use(v, p, i, j, k) in
+// the walk's order, so sums keep the order of a plain one-by-one walk.
+constexpr int SCAN_U = 4;
+template <class L, class F>
+__device__ __forceinline__ void scan_bbox(const int* b, const KmGeom& g, int lane, L&& load, F&& use) {
   const int i0 = b[0], i1 = b[1], j0 = b[2], j1 = b[3], k0 = b[4], k1 = b[5];
   if (i0 > i1) return;
   const int ej = j1 - j0 + 1, ek = k1 - k0 + 1;
   const int64_t nlines = (int64_t)(i1 - i0 + 1) * ej;
+  // this lane's n-th point: line q0 + n dq, offset kk + n dk within it
+  int64_t q0, dq;
+  int kk, dk, kspan;
   if (ek <= ISDF_WAVE) {
     const int lpp = ISDF_WAVE / ek;  // lines per pass
-    const int lo = lane / ek, kk = lane - lo * ek;
+    const int lo = lane / ek;
     if (lo >= lpp) return;
-    for (int64_t q = lo; q < nlines; q += lpp) {
-      int i = i0 + (int)(q / ej), j = j0 + (int)(q % ej), k = k0 + kk;
-      f(((int64_t)i * g.n1 + j) * g.n2 + k, i, j, k);
-    }
+    q0 = lo;
+    dq = lpp;
+    kk = lane - lo * ek;
+    dk = 0;
+    kspan = 1;
   } else {
-    for (int64_t q = 0; q < nlines; ++q) {
-      int i = i0 + (int)(q / ej), j = j0 + (int)(q % ej);
-      for (int k = k0 + lane; k <= k1; k += ISDF_WAVE) f(((int64_t)i * g.n1 + j) * g.n2 + k, i, j, k);
+    if (lane >= ek) return;
+    q0 = 0;
+    dq = 1;
+    kk = lane;
+    dk = ISDF_WAVE;
+    kspan = (ek - lane + ISDF_WAVE - 1) / ISDF_WAVE;  // points of this lane per line
+  }
+  const int64_t total = ((nlines - q0 + dq - 1) / dq) * kspan;
+  for (int64_t n0 = 0; n0 < total; n0 += SCAN_U) {
+    int64_t pp[SCAN_U];
+    int ii[SCAN_U], jj[SCAN_U], kq[SCAN_U];
+    decltype(load((int64_t)0)) v[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      const int64_t n = n0 + u < total ? n0 + u : total - 1;  // past the end: repeat the last point
+      const int64_t q = q0 + (n / kspan) * dq;
+      ii[u] = i0 + (int)(q / ej);
+      jj[u] = j0 + (int)(q % ej);
+      kq[u] = k0 + kk + (int)(n % kspan) * dk;
+      pp[u] = ((int64_t)ii[u] * g.n1 + jj[u]) * g.n2 + kq[u];
+      v[u] = load(pp[u]);
     }
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u)
+      if (n0 + u < total) use(v[u], pp[u], ii[u], jj[u], kq[u]);
   }
 }
 
@@ -375,15 +403,21 @@ __global__ __launch_bounds__(256) void km_update(KmArrays a, KmGeom g, int K, in
   if (mu >= K) return;
   int* b = a.bbox + 6 * (int64_t)mu;
   double sw = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-  scan_bbox(b, g, lane, [&](int64_t p, int i, int j, int k) {
-    if (a.labels[p] == mu) {
-      double wp = a.w[p];
-      sw += wp;
-      sx += wp * (double)i;
-      sy += wp * (double)j;
-      sz += wp * (double)k;
-    }
-  });
+  struct LabW {
+    int lab;
+    double w;
+  };
+  scan_bbox(
+      b, g, lane, [&](int64_t p) { return LabW{a.labels[p], a.w[p]}; },
+      [&](LabW v, int64_t, int i, int j, int k) {
+        if (v.lab == mu) {
+          const double wp = v.w;
+          sw += wp;
+          sx += wp * (double)i;
+          sy += wp * (double)j;
+          sz += wp * (double)k;
+        }
+      });
   sw = wave_sum(sw);
   sx = wave_sum(sx);
   sy = wave_sum(sy);
@@ -414,15 +448,17 @@ __global__ __launch_bounds__(256) void km_snap(KmArrays a, KmGeom g, int K, int3
                czm = a.cent[3 * (int64_t)mu + 2];
   double bd = INFINITY;
   int64_t bp = -1;
-  scan_bbox(a.bbox + 6 * (int64_t)mu, g, lane, [&](int64_t p, int i, int j, int k) {
-    if (a.labels[p] == mu) {
-      double d = sqd((double)i - cxm, (double)j - cym, (double)k - czm, g);
-      if (d < bd || (d == bd && p < bp)) {
-        bd = d;
-        bp = p;
-      }
-    }
-  });
+  scan_bbox(
+      a.bbox + 6 * (int64_t)mu, g, lane, [&](int64_t p) { return a.labels[p]; },
+      [&](int lab, int64_t p, int i, int j, int k) {
+        if (lab == mu) {
+          double d = sqd((double)i - cxm, (double)j - cym, (double)k - czm, g);
+          if (d < bd || (d == bd && p < bp)) {
+            bd = d;
+            bp = p;
+          }
+        }
+      });
   for (int o = 32; o > 0; o >>= 1) {
     double od = __shfl_xor(bd, o, ISDF_WAVE);
     int64_t op = __shfl_xor(bp, o, ISDF_WAVE);
