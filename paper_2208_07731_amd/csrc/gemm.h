@@ -30,8 +30,11 @@
 // (s_setprio).  With two waves per SIMD from two workgroups, the raised
 // priority lets one finish its MFMAs first and staggers the two, so that
 // one is less often waiting at its barrier or LDS stores while the other
-// does too (about 3 % on the large FP64 products).
+// does too (about 3 % on the large FP64 products; an epilogue type can opt
+// out, see EpiPrio).
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 
@@ -299,7 +302,8 @@ __device__ __forceinline__ void read2(const T* s, int x, int c, int s0, int lane
 //     the reads of slice i+1's first pair from the other buffer.
 // The order of the products into every accumulator is the plain k order,
 // as in mma_loop_flat.
-template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0>
+template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0,
+          bool PRIO = true>
 __device__ __forceinline__ void mma_loop_pp(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
                                             int N, int64_t kbeg, int64_t kend, T* smem,
                                             typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI],
@@ -363,14 +367,14 @@ __device__ __forceinline__ void mma_loop_pp(const Operand<TA>& A, const Operand<
             read2<T, LB, BN, BK>(nbuf + LA_::SIZE, xb + j * 16, 0, 0, lane, fb[nsl][j]);
         }
       }
-      __builtin_amdgcn_s_setprio(1);
+      if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
           for (int j = 0; j < Cfg::NI; ++j) MfmaT<T>::mma(fa[sl][i][t], fb[sl][j][t], acc[i][j]);
-      __builtin_amdgcn_s_setprio(0);
+      if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_sched_barrier(0);  // keep each pair's MFMAs in place
       if (p == NPAIR - 2 && next) {
         // slice i+1 (in registers since step i-1) into the other buffer, whose
@@ -469,9 +473,21 @@ __device__ __forceinline__ void mma_loop_flat(const Operand<TA>& A, const Operan
   if constexpr (FOLD > 0) fold_into<Cfg>(acc, *fold);
 }
 
+// Whether a kernel raises the wave priority around its MFMAs: yes, unless
+// the epilogue type says kPrio = false (measured per epilogue).
+template <class E, class = void>
+struct EpiPrio {
+  static constexpr bool value = true;
+};
+template <class E>
+struct EpiPrio<E, std::void_t<decltype(E::kPrio)>> {
+  static constexpr bool value = E::kPrio;
+};
+
 // The K loop of one operand pair: the software-pipelined form, except for
 // folded FP32 accumulators, whose extra FP64 set leaves no registers for it.
-template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0>
+template <class Cfg, class T, class TA, int LA, class TB, int LB, int BM, int BN, int BK, int FOLD = 0,
+          bool PRIO = true>
 __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>& B, int m0, int n0, int M,
                                          int N, int64_t kbeg, int64_t kend, T* smem,
                                          typename MfmaT<T>::acc_t (&acc)[Cfg::MI][Cfg::NI],
@@ -479,7 +495,7 @@ __device__ __forceinline__ void mma_loop(const Operand<TA>& A, const Operand<TB>
   if constexpr (FOLD > 0)
     mma_loop_flat<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD>(A, B, m0, n0, M, N, kbeg, kend, smem, acc, fold);
   else
-    mma_loop_pp<Cfg, T, TA, LA, TB, LB, BM, BN, BK, 0>(A, B, m0, n0, M, N, kbeg, kend, smem, acc, fold);
+    mma_loop_pp<Cfg, T, TA, LA, TB, LB, BM, BN, BK, 0, PRIO>(A, B, m0, n0, M, N, kbeg, kend, smem, acc, fold);
 }
 
 // Tile coordinates handed to epilogues.
@@ -552,7 +568,8 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh
 #pragma unroll
       for (int j = 0; j < Cfg::NI; ++j) f0.v[i][j] = d4v{0, 0, 0, 0};
   }
-  mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD>(A0, B0, m0, n0, sh.M, sh.N, kbeg, kend, smem, acc0, &f0);
+  mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD, EpiPrio<Epi>::value>(A0, B0, m0, n0, sh.M, sh.N, kbeg, kend, smem,
+                                                                         acc0, &f0);
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -572,7 +589,8 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_kernel(GemmShape sh
         for (int j = 0; j < Cfg::NI; ++j) f1.v[i][j] = d4v{0, 0, 0, 0};
     }
     __syncthreads();
-    mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD>(A1, B1, m0, n0, sh.M, sh.N, 0, K1, smem, acc1, &f1);
+    mma_loop<Cfg, T, TA, LA, TB, LB, BM, BN, BK, FOLD, EpiPrio<Epi>::value>(A1, B1, m0, n0, sh.M, sh.N, 0, K1, smem,
+                                                                           acc1, &f1);
     if constexpr (FOLD > 0)
       epi.template apply2<Cfg>(f0.v, f1.v, at);
     else
