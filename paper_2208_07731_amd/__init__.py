@@ -8,4 +8,5 @@ from .api import (ISDFError, KMeansResult, QRCPResult, cluster_residual, exchang
                   fit_backward, fit_residual, kmeans, poisson, qrcp)
 from .autograd import ISDFFit, ISDFLoss  # noqa: F401
 
-__all__ = ["kmeans", "fit", "fit_backward", "ISDFFit", "ISDFLoss", "ISDFError", "KMeansResult"]
+__all__ = ["kmeans", "fit", "fit_backward", "fit_residual", "cluster_residual", "poisson", "exchange", "qrcp",
+           "ISDFFit", "ISDFLoss", "ISDFError", "KMeansResult", "QRCPResult"]
