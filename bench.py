@@ -273,6 +273,21 @@ def weight_study(phi, psi, wl, d, kinds) -> dict:
     return out
 
 
+def _host_description() -> dict:
+    """CPU model and the thread settings the oracle's numpy/scipy ran with."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    return {"cpu_model": model, "nproc": os.cpu_count(), "threads_env": {k: v for k, v in env.items() if v}}
+
+
 def cpu_baseline(d, idx, iters_run: int) -> dict:
     """The FP64 oracle on a bounded sample of the same workload, scaled to
     one full step (ms): weight at full size, two K-means rounds at full size
@@ -318,6 +333,7 @@ def cpu_baseline(d, idx, iters_run: int) -> dict:
     cores = len(os.sched_getaffinity(0))
     return {
         "value": round(total * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+        "host": _host_description(),
         "sample": (f"numpy/scipy FP64 oracle on {cores} host threads: weight at full size, 2 of "
                    f"{iters_run + 1} K-means rounds at full size, fit and fused adjoint on sub-problems of "
                    f"N_mu+1024 and N_mu+3072 grid rows, extrapolated linearly in rows and rounds"),
