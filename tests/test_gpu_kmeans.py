@@ -180,3 +180,25 @@ def test_kmeans_water64_one_round_teacher_forced():
     assert np.array_equal(r.labels.cpu().numpy()[ok], km["labels"][ok])
     assert np.max(np.abs(r.centroids.cpu().numpy() - km["centroids"])) <= 1e-12 * wl.n
     assert np.array_equal(r.idx.cpu().numpy(), km["idx"])
+
+
+def test_kmeans_sio2_weight_and_one_round():
+    """Full-size SiO2-like grid (72^3 = 373248 points, N_mu = 3072; Phi the
+    first 192 of Psi's 384 columns, read through the leading dimension):
+    the SSM weight of both orbital sets against the oracle, then one round
+    from the oracle's seeds and weight, labels (outside near ties),
+    centroids and points against the oracle."""
+    d = synth.make_workload("sio2")
+    wl = d["wl"]
+    psi_t = dev(d["psi"])
+    phi_t = psi_t[:, : wl.n_phi]  # leading dimension n_psi
+    w = oracle.weight(d["phi"], d["psi"])
+    r0 = isdf.kmeans(phi_t, psi_t, wl.n_mu, d["c0"], 0, grid=wl.n)
+    assert np.max(np.abs(r0.w.cpu().numpy() - w) / w) <= 1e-13
+    r = isdf.kmeans(None, None, wl.n_mu, d["c0"], 1, w=dev(w), grid=wl.n)
+    km = oracle.kmeans(wl.n, w, d["c0"], 1)
+    ok = ~km["near_tie_mask"]
+    print(f"sio2: {int((~ok).sum())} near-tie points of {wl.n_r}")
+    assert np.array_equal(r.labels.cpu().numpy()[ok], km["labels"][ok])
+    assert np.max(np.abs(r.centroids.cpu().numpy() - km["centroids"])) <= 1e-12 * wl.n
+    assert np.array_equal(r.idx.cpu().numpy(), km["idx"])
