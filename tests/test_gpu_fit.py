@@ -115,6 +115,36 @@ def test_fit_matches_hand_derived_golden(golden_theta):
 
 
 @pytest.fixture(scope="module")
+def water64_case():
+    """64-water workload (64^3 grid, N_e = 256, Psi = Phi, N_mu = 2048),
+    seeded interpolation points and 256 sampled rows with their oracle
+    Theta."""
+    d = synth.make_workload("water64")
+    wl = d["wl"]
+    rng = np.random.default_rng(31)
+    idx = synth.init_centroids(d["env"] ** 2, wl.n, wl.n_mu, 3031)
+    idx = ((idx[:, 0] * wl.n + idx[:, 1]) * wl.n + idx[:, 2]).astype(np.int32)
+    rows = np.sort(rng.choice(wl.n_r, 256, replace=False))
+    ref = oracle.fit(d["phi"], d["phi"], idx, rows=rows)
+    kappa = oracle.cc_condition(d["phi"], d["phi"], idx)
+    return dict(d=d, wl=wl, idx=idx, rows=rows, ref=ref, kappa=kappa)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "fp16x3"])
+def test_fit_water64_sampled_rows(water64_case, prec):
+    """Full-size 64-water fit (the benchmark's shape, whole grid in one
+    block): sampled rows of the real Theta against the oracle, FP64 to the
+    kappa floor and the lower orbital precisions to 1e-6."""
+    c = water64_case
+    theta, _, info = isdf.fit(dev(c["d"]["phi"]), None, dev(c["idx"]), prec=prec)
+    got = theta[torch.as_tensor(c["rows"]).cuda()].cpu().numpy()
+    err = rel(got, c["ref"]["theta"].real)
+    print(f"water64 {prec} theta rel err {err:.3e} (kappa {c['kappa']:.2e})")
+    assert err <= (fp64_tol(c["kappa"]) if prec == "fp64" else 1e-6)
+    assert info["status"] == 0
+
+
+@pytest.fixture(scope="module")
 def sio2_case():
     """SiO2-like workload (72^3 grid, N_phi = 192, N_psi = 384 sharing the
     first 192 columns, N_mu = 3072, complex), seeded interpolation points and
