@@ -144,6 +144,31 @@ def test_fit_water64_sampled_rows(water64_case, prec):
     assert info["status"] == 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+def test_fit_backward_water64_gradient_rows(water64_case, prec):
+    """Full-size 64-water fused-loss adjoint (the benchmark's shape and
+    field g, whole grid in one block): gradient rows of Phi at the sampled
+    non-interpolation points against the oracle's sub-problem."""
+    c = water64_case
+    d, wl = c["d"], c["wl"]
+    sample = np.setdiff1d(c["rows"], c["idx"])
+    phi_t = dev(d["phi"])
+    idx_t = dev(c["idx"])
+    g = d["g"]
+    _, minv, _ = isdf.fit(phi_t, None, idx_t, nrows=0)
+    dphi, _, loss, info = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(g), prec=prec)
+    got = dphi[torch.as_tensor(sample).cuda()].cpu().numpy()
+    del dphi
+    sub = np.concatenate([c["idx"], sample])
+    phi_sub = np.ascontiguousarray(d["phi"][sub])
+    ref = oracle.fit_backward(phi_sub, phi_sub, np.arange(wl.n_mu), g=g[sub])
+    err = rel(got, ref["dphi"][wl.n_mu:])
+    tol = max(1e-11, 1e2 * c["kappa"] * EPS) if prec == "fp64" else 1e-5
+    print(f"water64 {prec} adjoint rows: dphi {err:.3e} (tol {tol:.1e}, {sample.size} rows)")
+    assert err <= tol
+    assert info["status"] == 0 and np.isfinite(loss.item()) and loss.item() > 0
+
+
 @pytest.fixture(scope="module")
 def sio2_case():
     """SiO2-like workload (72^3 grid, N_phi = 192, N_psi = 384 sharing the
