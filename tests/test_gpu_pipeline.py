@@ -146,3 +146,43 @@ def test_saved_gram_adjoint_bitwise(prec, dtype, general):
     a.enqueue()
     a.check()
     assert torch.equal(a.dphi, b.dphi) and a.loss.item() == b.loss.item()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
+def test_water64_step_as_benchmarked(prec):
+    """The benchmark's step at full size (64-water: 50 K-means rounds, fit
+    with the Gram blocks kept, fused-loss adjoint from them, one block):
+    with the points it chose, sampled rows of Theta and of dPhi against the
+    oracle (the gradient rows on the sub-problem of the interpolation rows
+    plus the sampled ones)."""
+    import synth
+
+    d = synth.make_workload("water64")
+    wl = d["wl"]
+    phi, g = d["phi"], d["g"]
+    st = ISDFStep(dev(phi), None, wl.n_mu, d["c0"], wl.kmeans_iters, g=dev(g), prec=prec)
+    assert st.save_gram
+    st.enqueue()
+    info = st.check()
+    idx = st.idx.cpu().numpy()
+    assert idx.min() >= 0 and len(np.unique(idx)) == wl.n_mu
+    rng = np.random.default_rng(64)
+    rows = np.sort(rng.choice(wl.n_r, 256, replace=False))
+    kappa = oracle.cc_condition(phi, phi, idx)
+    ref = oracle.fit(phi, phi, idx, rows=rows)["theta"].real
+    got = st.theta[torch.as_tensor(rows).cuda()].cpu().numpy()
+    err_t = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    sample = np.setdiff1d(rows, idx)
+    sub = np.concatenate([idx, sample])
+    phi_sub = np.ascontiguousarray(phi[sub])
+    refb = oracle.fit_backward(phi_sub, phi_sub, np.arange(wl.n_mu), g=g[sub])
+    gotb = st.dphi[torch.as_tensor(sample).cuda()].cpu().numpy()
+    want = refb["dphi"][wl.n_mu:]
+    err_g = np.linalg.norm(gotb - want) / np.linalg.norm(want)
+    print(f"water64 step {prec}: theta {err_t:.3e}, dphi rows {err_g:.3e} (kappa {kappa:.2e})")
+    if prec == "fp64":
+        assert err_t <= max(1e-12, 4 * kappa * EPS)
+        assert err_g <= max(1e-11, 1e2 * kappa * EPS)
+    else:
+        assert err_t <= 1e-6 and err_g <= 1e-5
+    assert info["backward"]["status"] == 0 and np.isfinite(st.loss.item())
