@@ -83,3 +83,29 @@ def test_exchange_chain_exact_when_every_point_interpolates():
     V = isdf.poisson(theta, n, h)
     W = isdf.exchange(p, q, i, V, grid=n)
     assert rel(W.cpu().numpy(), oracle.exchange_direct(phi, psi, n, h)) <= 1e-9
+
+
+def test_exchange_water64_sampled_rows():
+    """Full-size 64-water exchange (N_r = 262144, N_e = 256, N_mu = 2048,
+    r-blocks of 65536) with seeded real potentials: W at 256 sampled rows
+    against the oracle (each row of W depends on its own row of Phi and V
+    and on Phi_mu, Psi_mu only)."""
+    import synth
+
+    d = synth.make_workload("water64")
+    wl = d["wl"]
+    phi = d["phi"]
+    rng = np.random.default_rng(6401)
+    idx = np.sort(rng.choice(wl.n_r, wl.n_mu, replace=False)).astype(np.int32)
+    v = rng.standard_normal((wl.n_r, wl.n_mu))
+    rows = np.sort(rng.choice(wl.n_r, 256, replace=False))
+    p = dev(phi)
+    W = isdf.exchange(p, p, dev(idx), dev(v))
+    got = W[torch.as_tensor(rows).cuda()].cpu().numpy()
+    del W
+    sub = np.concatenate([idx, rows])
+    phi_sub = np.ascontiguousarray(phi[sub])
+    ref = oracle.exchange(phi_sub, phi_sub, np.arange(wl.n_mu), v[sub])[wl.n_mu:]
+    err = rel(got, ref)
+    print(f"water64 exchange rows rel err {err:.3e}")
+    assert err <= 1e-13
