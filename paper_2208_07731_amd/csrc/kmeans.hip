@@ -208,9 +208,24 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
 
   double d1 = INFINITY, d2 = INFINITY;
   int lab = 0;
-  // pass 1: U = min over centroids of the farthest brick distance
+  const int64_t p = ((int64_t)pi * g.n1 + pj) * g.n2 + pk;
+  // pass 1: U, an upper bound of every brick point's nearest distance.  After
+  // the first round: the largest distance of a point to its current cluster's
+  // centroid (labels from the previous round, centroids just updated);
+  // first round: the smallest over centroids of the farthest brick distance.
   double U = INFINITY;
-  for (int c0 = 0; c0 < K; c0 += CTILE) {
+  if (t > 0) {
+    double own = -INFINITY;
+    if (valid) {
+      const int old = a.labels[p];
+      own = sqd(px - a.cent[3 * (int64_t)old], py - a.cent[3 * (int64_t)old + 1],
+                pz - a.cent[3 * (int64_t)old + 2], g);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) own = fmax(own, __shfl_xor(own, o, ISDF_WAVE));
+    U = own;
+  }
+  for (int c0 = 0; c0 < K && t == 0; c0 += CTILE) {
     const int cn = min(CTILE, K - c0);
     __syncthreads();
     for (int i = threadIdx.x; i < cn; i += ASSIGN_THREADS) {
@@ -225,11 +240,13 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
       U = fmin(U, ub);
     }
   }
+  if (t == 0) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) U = fmin(U, __shfl_xor(U, o, ISDF_WAVE));
+    for (int o = 32; o > 0; o >>= 1) U = fmin(U, __shfl_xor(U, o, ISDF_WAVE));
+  }
   const double cut = U * margin;
   // pass 2: survivors of each tile, in increasing index, then the exact scan
-  const bool one_tile = K <= CTILE;
+  const bool one_tile = K <= CTILE && t == 0;  // the tile is still in LDS from pass 1
   for (int c0 = 0; c0 < K; c0 += CTILE) {
     const int cn = min(CTILE, K - c0);
     if (!one_tile) {
@@ -276,7 +293,6 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
     }
   }
 
-  const int64_t p = ((int64_t)pi * g.n1 + pj) * g.n2 + pk;
   double jv = 0.0;
   bool chg = false, tie = false, nr_tie = false;
   if (valid) {
