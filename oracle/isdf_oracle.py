@@ -288,7 +288,8 @@ def fit_theta(phi, psi, idx, rows=None) -> np.ndarray:
 
 
 def cc_condition(phi, psi, idx) -> float:
-    """2-norm condition number of C C^H (diagnostic)."""
+    """2-norm condition number of C C^H (Sec. 2.4's matrix), from its
+    eigenvalues; a diagnostic printed beside parity errors."""
     ev = np.linalg.eigvalsh(_cc(phi, psi, idx))
     return float(ev[-1] / ev[0]) if ev[0] > 0 else float("inf")
 

@@ -213,7 +213,8 @@ __global__ void mbar_hadamard(const double* __restrict__ P, const double* __rest
 // Q[2 mu + c][2 i + c'] = sum_r Abar_c(r, mu) X_c'(r, i).
 template <class TS>
 __global__ void scatter_rows(TS* __restrict__ dX, int64_t ld, int n, const int32_t* __restrict__ idx, int n_mu,
-                             const double* __restrict__ Q, const double* __restrict__ T1, const int* abort) {
+                             int64_t nr, const double* __restrict__ Q, const double* __restrict__ T1,
+                             const int* abort) {
   if (*abort) return;
   const int64_t total = (int64_t)n_mu * n;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -222,7 +223,9 @@ __global__ void scatter_rows(TS* __restrict__ dX, int64_t ld, int n, const int32
     const int64_t q0 = (int64_t)(2 * mu) * (2 * n), q1 = q0 + 2 * n;
     const double re = Q[q0 + 2 * i] + Q[q1 + 2 * i + 1] + T1[(int64_t)mu * 2 * n + 2 * i];
     const double im = Q[q0 + 2 * i + 1] - Q[q1 + 2 * i] + T1[(int64_t)mu * 2 * n + 2 * i + 1];
-    TS* p = dX + 2 * ((int64_t)idx[mu] * ld + i);
+    const int64_t row = idx[mu];
+    if (row < 0 || row >= nr) continue;  // reported by check_idx, which also aborts the call
+    TS* p = dX + 2 * (row * ld + i);
     const double2 old = Cplx<TS>::load(p);
     Cplx<TS>::store(p, old.x + re, old.y + im);
   }
@@ -316,6 +319,7 @@ static AdjPlanes carve_adj(Carver& c, isdf_prec prec, int n_phi, int n_psi, bool
 
 struct BwdPlan {
   FitState* st;
+  int* marker;   // [N_r] occupancy of the interpolation rows (check_idx)
   void *Ephi, *Epsi, *Fphi, *Fpsi, *Xphi, *Xpsi;
   double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart, *W2;
   double* amax;  // [4] max |Phi|, |Psi|, |Abar|, |Bbar| (binary16 split)
@@ -346,6 +350,7 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   const int64_t n1 = aliased ? n_mu : 2 * (int64_t)n_mu;
   const int nmax = n_phi > n_psi ? n_phi : n_psi;
   P.st = c.take<FitState>(1);
+  P.marker = c.take<int>(nr);
   P.amax = c.take<double>(4);
   P.sc = c.take<double>(12);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
@@ -428,8 +433,8 @@ static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC
 // Mbar terms of one orbital set at the interpolation rows (small: N_mu rows).
 template <int PREC, class TS>
 static bool orbital_fix(const double* dAbar, int n_mu, const typename Prec<PREC>::E* F,
-                        const typename Prec<PREC>::E* Xmu, int n, TS* dX, int64_t ld_dx, const int32_t* idx, double* Q,
-                        double* T1, const int* ab, hipStream_t s) {
+                        const typename Prec<PREC>::E* Xmu, int n, TS* dX, int64_t ld_dx, const int32_t* idx, int64_t nr,
+                        double* Q, double* T1, const int* ab, hipStream_t s) {
   typedef typename Prec<PREC>::E T;
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if (!tgemm<T, KC, KC>(n_mu, 2 * n, two_mu, dAbar, two_mu, F, two_mu, T1, 2 * (int64_t)n, 1.0, 0.0, ab, s))
@@ -438,7 +443,7 @@ static bool orbital_fix(const double* dAbar, int n_mu, const typename Prec<PREC>
                         ab, s))
     return false;
   hipLaunchKernelGGL(scatter_rows<TS>, dim3(blocks_for((int64_t)n_mu * n)), dim3(256), 0, s, dX, ld_dx, n, idx, n_mu,
-                     (const double*)Q, (const double*)T1, ab);
+                     nr, (const double*)Q, (const double*)T1, ab);
   return launch_ok();
 }
 
@@ -453,6 +458,11 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   const int* ab = &P.st->abort;
   typedef typename Prec<PREC>::E T;
   hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
+  // interpolation indices must be distinct grid points: every launch that
+  // reads or writes rows through idx is a no-op once check_idx has aborted
+  // the call, and fit_finish reports ISDF_E_BAD_IDX
+  if (!fill<int>(P.marker, nr, 0, s)) return ISDF_E_HIP;
+  hipLaunchKernelGGL(check_idx, dim3((unsigned)ceil_div(n_mu, 256)), dim3(256), 0, s, idx, n_mu, nr, P.marker, P.st);
   T *Ephi = (T*)P.Ephi, *Fphi = (T*)P.Fphi, *Xphi = (T*)P.Xphi;
   T *Epsi = aliased ? Ephi : (T*)P.Epsi, *Fpsi = aliased ? Fphi : (T*)P.Fpsi, *Xpsi = aliased ? Xphi : (T*)P.Xpsi;
   if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
@@ -558,9 +568,9 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   hipLaunchKernelGGL(mbar_hadamard, dim3(blocks_for((int64_t)n_mu * n_mu)), dim3(256), 0, s, (const double*)P.P,
                      (const double*)P.Amu, (const double*)P.Bmu, P.dA, P.dB, n_mu, aliased ? 1 : 0, ab);
   if (!launch_ok()) return ISDF_E_HIP;
-  if (!orbital_fix<PREC, TS>(P.dA, n_mu, Fphi, Xphi, n_phi, dphi, ld_dphi, idx, P.Qphi, P.T1, ab, s))
+  if (!orbital_fix<PREC, TS>(P.dA, n_mu, Fphi, Xphi, n_phi, dphi, ld_dphi, idx, nr, P.Qphi, P.T1, ab, s))
     return ISDF_E_HIP;
-  if (!aliased && !orbital_fix<PREC, TS>(P.dB, n_mu, Fpsi, Xpsi, n_psi, dpsi, ld_dpsi, idx, P.Qpsi, P.T1, ab, s))
+  if (!aliased && !orbital_fix<PREC, TS>(P.dB, n_mu, Fpsi, Xpsi, n_psi, dpsi, ld_dpsi, idx, nr, P.Qpsi, P.T1, ab, s))
     return ISDF_E_HIP;
   if (aliased && dpsi != dphi) {
     hipLaunchKernelGGL((copy_rows<TS>), dim3(blocks_for(nr * 2 * n_phi)), dim3(256), 0, s, dpsi, ld_dpsi,

@@ -162,12 +162,18 @@ __global__ void km_init(KmArrays a, const double* __restrict__ c0, int K, int T,
 // ------------------------------------------------------------------ assign
 // Exact per-brick candidate pruning.  For the brick's bounding box B and a
 // centroid c: lb(c) = min_{p in B} D(p, c), ub(c) = max_{p in B} D(p, c).
-// U = min_c ub(c) bounds every point's nearest distance, so a centroid with
-// lb(c) > U is strictly farther than some centroid for every point of the
-// brick and can be skipped.  The test uses U (1 + margin) with margin well
-// above rounding and above the near-tie band, so labels, exact ties and
-// near-tie counts are those of the full scan.  Survivors are evaluated in
-// increasing centroid order (lowest index wins ties).
+// U is an upper bound of every brick point's nearest distance d1(p):
+//  * first round: U = min_c ub(c), since d1(p) <= D(p, c) <= ub(c) for any c;
+//  * later rounds: U = max_{p in B} D(p, c(old(p))), the distance of each
+//    point to the centroid of the cluster it was given in the previous round,
+//    evaluated with the centroids as they are now (just updated); that is a
+//    distance to one of the current centroids, so d1(p) <= D(p, c(old(p))) <= U
+//    however far that centroid moved.
+// A centroid with lb(c) > U is then strictly farther than some centroid for
+// every point of the brick and can be skipped.  The test uses U (1 + margin)
+// with margin well above rounding and above the near-tie band, so labels,
+// exact ties and near-tie counts are those of the full scan.  Survivors are
+// evaluated in increasing centroid order (lowest index wins ties).
 constexpr int SURV = 128;  // per-wavefront survivor list
 
 __device__ __forceinline__ double axis_lb(double c, double lo, double hi) {

@@ -259,3 +259,27 @@ def test_out_of_range_enumerations_are_rejected(bad):
                                 None, FAKE, FAKE, 1 << 30, None) == L.E_ARG
     assert lib.isdf_cluster_residual(C.byref(g), bad, FAKE, 4, 4, FAKE, 4, 4, FAKE, FAKE, 5, FAKE, FAKE, 1 << 20,
                                      None) == L.E_ARG
+
+
+def test_one_hip_runtime_in_the_process():
+    """Loading the library after torch maps a single HIP runtime: the one
+    torch ships (same soname), not a second copy from /opt/rocm, so the
+    streams and device memory torch hands over belong to the runtime the
+    library's launches go through.  Checked in a fresh interpreter."""
+    import subprocess
+    import sys
+
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2208_07731_amd import _lib as L\n"
+        "L.load()\n"
+        "paths = set()\n"
+        "for line in open('/proc/self/maps'):\n"
+        "    f = line.split()\n"
+        "    if len(f) >= 6 and 'libamdhip64' in f[5]:\n"
+        "        paths.add(f[5])\n"
+        "print(len(paths), sorted(paths))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    n = int(out.stdout.split()[0])
+    assert n == 1, out.stdout

@@ -13,6 +13,14 @@ pytestmark = pytest.mark.gpu
 isdf = pytest.importorskip("paper_2208_07731_amd")
 
 
+# Parity bars (relative Frobenius norm against the FP64 oracle): FP64
+# gradients and loss within 1e-11 whatever the conditioning of C C^H (kappa
+# is printed as a diagnostic only); orbital contractions in FP32 or a split
+# precision within 1e-5.
+FP64_GRAD = 1e-11
+MIXED_GRAD = 1e-5
+
+
 def dev(x):
     return torch.as_tensor(np.ascontiguousarray(x)).cuda()
 
@@ -37,7 +45,8 @@ def test_backward_fused_loss_aliased_water8(water8, water8_idx):
     phi_t, idx_t = dev(phi), dev(water8_idx.astype(np.int32))
     _, minv, _ = isdf.fit(phi_t, None, idx_t, nrows=0)
     dphi, dpsi, loss, info = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(g))
-    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    tol = FP64_GRAD
+    print(f"water8 fused adjoint: dphi {rel(dphi.cpu().numpy(), ref['dphi']):.3e} (kappa {kappa:.2e})")
     assert abs(loss.item() - ref["loss"]) <= tol * ref["loss"]
     assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
     assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
@@ -65,7 +74,8 @@ def test_backward_general_upstream_complex(rblock):
     dphi, dpsi, _, _ = isdf.fit_backward(t[:, :7], t[:, 7:16], dev(idx), minv, theta_bar=dev(tbar), grid=(5, 6, 7),
                                          rblock=rblock)
     kappa = oracle.cc_condition(phi, psi, idx)
-    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    tol = FP64_GRAD
+    print(f"kappa {kappa:.2e}")
     assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
     assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
 
@@ -80,7 +90,8 @@ def test_backward_fused_complex_multi_block():
     dphi, dpsi, loss, _ = isdf.fit_backward(t[:, :7], t[:, 7:16], dev(idx), minv, g=dev(g), grid=(5, 6, 7),
                                             rblock=50)
     kappa = oracle.cc_condition(phi, psi, idx)
-    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    tol = FP64_GRAD
+    print(f"kappa {kappa:.2e}")
     assert abs(loss.item() - ref["loss"]) <= tol * ref["loss"]
     assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
     assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
@@ -95,7 +106,8 @@ def test_backward_aliased_general_upstream_real():
     _, minv, _ = isdf.fit(t, None, dev(idx), grid=(5, 6, 7), nrows=0)
     dphi, dpsi, _, _ = isdf.fit_backward(t, None, dev(idx), minv, theta_bar=dev(tbar), grid=(5, 6, 7), rblock=100)
     kappa = oracle.cc_condition(phi, phi, idx)
-    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    tol = FP64_GRAD
+    print(f"kappa {kappa:.2e}")
     assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
     assert torch.equal(dphi, dpsi)
 
@@ -111,8 +123,10 @@ def test_backward_fp32_gram_water8(water8, water8_idx, dtype):
     phi_t, idx_t = dev(phi), dev(water8_idx.astype(np.int32))
     _, minv, _ = isdf.fit(phi_t, None, idx_t, prec="fp32", nrows=0)
     dphi, _, loss, _ = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(g), prec="fp32")
-    assert rel(dphi.cpu().numpy().astype(np.complex128), ref["dphi"]) <= 1e-4
-    assert abs(loss.item() - ref["loss"]) <= 1e-5 * ref["loss"]
+    err = rel(dphi.cpu().numpy().astype(np.complex128), ref["dphi"])
+    print(f"fp32 {dtype} dphi rel err {err:.3e}")
+    assert err <= MIXED_GRAD
+    assert abs(loss.item() - ref["loss"]) <= 1e-6 * ref["loss"]
 
 
 def test_autograd_fit_matches_oracle():
@@ -227,7 +241,7 @@ def test_backward_split_precision_water8(water8, water8_idx, prec):
     dphi, _, loss, _ = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(g), prec=prec, rblock=5000)
     err = rel(dphi.cpu().numpy(), ref["dphi"])
     print(f"{prec} dphi rel err {err:.3e}, loss rel err {abs(loss.item() - ref['loss']) / ref['loss']:.3e}")
-    assert err <= 1e-5
+    assert err <= MIXED_GRAD
     assert abs(loss.item() - ref["loss"]) <= 1e-6 * ref["loss"]
 
 
@@ -242,9 +256,9 @@ def test_backward_split_precision_complex(prec):
     dphi, dpsi, loss, _ = isdf.fit_backward(t[:, :7], t[:, 7:16], dev(idx), minv, g=dev(g), grid=(5, 6, 7),
                                             rblock=64, prec=prec)
     kappa = oracle.cc_condition(phi, psi, idx)
-    tol = max(1e-5, 1e-7 * kappa)
-    assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
-    assert rel(dpsi.cpu().numpy(), ref["dpsi"]) <= tol
+    e_phi, e_psi = rel(dphi.cpu().numpy(), ref["dphi"]), rel(dpsi.cpu().numpy(), ref["dpsi"])
+    print(f"{prec} complex adjoint: dphi {e_phi:.3e}, dpsi {e_psi:.3e} (kappa {kappa:.2e})")
+    assert e_phi <= MIXED_GRAD and e_psi <= MIXED_GRAD
 
 
 @pytest.mark.parametrize("general", [True, False])
@@ -299,5 +313,57 @@ def test_backward_from_kept_gram_blocks_upstream(general):
     if general:
         assert torch.equal(dpsi, want[1])
     kappa = oracle.cc_condition(phi, psi, idx)
-    tol = max(1e-11, 1e2 * kappa * np.finfo(float).eps)
+    tol = FP64_GRAD
+    print(f"kappa {kappa:.2e}")
     assert rel(dphi.cpu().numpy(), ref["dphi"]) <= tol
+
+
+@pytest.mark.parametrize("case", ["negative", "past_end", "repeated"])
+@pytest.mark.parametrize("kept", [False, True])
+def test_backward_rejects_bad_interpolation_index(case, kept):
+    """An index that is not a distinct grid point (the -1 of an empty K-means
+    cluster, one past the grid, a repeat) is reported as ISDF_E_BAD_IDX with
+    its position, by the recomputing adjoint and by the one from kept Gram
+    blocks, and nothing is read or written through it (the call is a no-op
+    after the check)."""
+    from paper_2208_07731_amd import _lib as L
+    import ctypes as C
+
+    rng, big, idx = tiny(21)
+    nr, n_mu = big.shape[0], len(idx)
+    t = dev(big)
+    tp, ts = t[:, :7], t[:, 7:16]
+    good = dev(idx)
+    _, minv, _ = isdf.fit(tp, ts, good, grid=(5, 6, 7), nrows=0)
+    bad = idx.copy()
+    pos = 5
+    bad[pos] = {"negative": -1, "past_end": nr, "repeated": bad[2]}[case]
+    bad_t = dev(bad)
+    g = dev(rng.uniform(0.5, 1.5, nr))
+    if not kept:
+        _, _, _, info = isdf.fit_backward(tp, ts, bad_t, minv, g=g, grid=(5, 6, 7), rblock=64, check=False)
+    else:
+        lib = L.load()
+        gr = L.make_grid((5, 6, 7))
+        s = torch.cuda.current_stream().cuda_stream
+        G = torch.empty(nr, 2 * n_mu, dtype=torch.float64, device="cuda")
+        A = torch.empty(nr, 2 * n_mu, dtype=torch.float64, device="cuda")
+        B = torch.empty(nr, 2 * n_mu, dtype=torch.float64, device="cuda")
+        zws = torch.empty(lib.isdf_zc_workspace(n_mu, 7, 9, 0, 0, nr), dtype=torch.uint8, device="cuda")
+        assert lib.isdf_zc_ab(C.byref(gr), L.C128, tp.data_ptr(), tp.stride(0), 7, ts.data_ptr(), ts.stride(0), 9,
+                              good.data_ptr(), n_mu, 0, 0, nr, G.data_ptr(), 2 * n_mu, A.data_ptr(), B.data_ptr(),
+                              zws.data_ptr(), zws.numel(), s) == L.OK
+        bws = torch.empty(lib.isdf_fit_backward_gram_workspace(C.byref(gr), n_mu, 7, 9, 0, 0, 64), dtype=torch.uint8,
+                          device="cuda")
+        dphi = torch.full((nr, 7), 7.0, dtype=torch.complex128, device="cuda")
+        dpsi = torch.full((nr, 9), 7.0, dtype=torch.complex128, device="cuda")
+        infob = torch.zeros(C.sizeof(L.FitInfo), dtype=torch.uint8, device="cuda")
+        assert lib.isdf_fit_backward_gram(C.byref(gr), L.C128, tp.data_ptr(), tp.stride(0), 7, ts.data_ptr(),
+                                          ts.stride(0), 9, bad_t.data_ptr(), n_mu, 0, minv.data_ptr(), None, 0,
+                                          g.data_ptr(), dphi.data_ptr(), 7, dpsi.data_ptr(), 9, None, 64,
+                                          G.data_ptr(), A.data_ptr(), B.data_ptr(), infob.data_ptr(), bws.data_ptr(),
+                                          bws.numel(), s) == L.OK
+        torch.cuda.synchronize()
+        raw = L.FitInfo.from_buffer_copy(bytes(infob.cpu().numpy()))
+        info = {f: getattr(raw, f) for f, _ in L.FitInfo._fields_}
+    assert info["status"] == L.E_BAD_IDX and info["bad_idx"] == pos, info

@@ -67,7 +67,9 @@ def test_exchange_chain_water8(water8_x):
     V = isdf.poisson(theta, x["wl"].n, (x["h"],) * 3)
     W = isdf.exchange(p, p, i, V)
     kappa = oracle.cc_condition(x["phi"], x["phi"], x["idx"])
-    assert rel(W.cpu().numpy(), x["ref"]) <= max(1e-12, 10 * kappa * EPS)
+    err = rel(W.cpu().numpy(), x["ref"])
+    print(f"water8 exchange chain rel err {err:.3e} (kappa {kappa:.2e})")
+    assert err <= 1e-12
 
 
 def test_exchange_chain_exact_when_every_point_interpolates():

@@ -33,11 +33,15 @@ def water8_fit(water8):
     return dict(phi=phi, idx=idx, ref=ref, kappa=kappa, wl=wl)
 
 
-def fp64_tol(kappa):
-    """Rounding-order differences in G and in the factorisation of C C^H move
-    Theta by about kappa * eps relative; 1e-12 is the target, kappa * eps the
-    floor below which no two FP64 orderings can be compared."""
-    return max(1e-12, 4.0 * kappa * EPS)
+# Parity bars (relative Frobenius norm against the FP64 oracle).  FP64:
+# Theta within 1e-12 and gradients within 1e-11 whatever the conditioning of
+# C C^H (measured errors are 1e-15 .. 1e-14 at every size); orbital
+# contractions in FP32 or a split precision: Theta within 1e-6, gradients
+# within 1e-5.  kappa(C C^H) is printed as a diagnostic only.
+FP64_THETA = 1e-12
+FP64_GRAD = 1e-11
+MIXED_THETA = 1e-6
+MIXED_GRAD = 1e-5
 
 
 def test_fit_fp64_water8(water8_fit):
@@ -45,7 +49,9 @@ def test_fit_fp64_water8(water8_fit):
     theta, minv, info = isdf.fit(dev(f["phi"]), None, dev(f["idx"].astype(np.int32)))
     th = theta.cpu().numpy()
     assert th.dtype == np.float64
-    assert rel(th, f["ref"]["theta"].real) <= fp64_tol(f["kappa"])
+    err = rel(th, f["ref"]["theta"].real)
+    print(f"water8 fp64 theta rel err {err:.3e} (kappa {f['kappa']:.2e})")
+    assert err <= FP64_THETA
     assert info["status"] == 0 and info["pivot"] == -1
     # minv against the oracle's inverse of C C^H
     M = f["ref"]["M"].real
@@ -88,7 +94,9 @@ def test_fit_fp64_complex_ragged():
     kappa = oracle.cc_condition(big[:, :7], big[:, 7:16], idx)
     th = theta.cpu().numpy()
     assert th.dtype == np.complex128
-    assert rel(th, ref["theta"]) <= fp64_tol(kappa)
+    err = rel(th, ref["theta"])
+    print(f"complex ragged fp64 theta rel err {err:.3e} (kappa {kappa:.2e})")
+    assert err <= FP64_THETA
 
 
 def test_fit_fp64_complex_swap_conjugates():
@@ -133,14 +141,14 @@ def water64_case():
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "fp16x3"])
 def test_fit_water64_sampled_rows(water64_case, prec):
     """Full-size 64-water fit (the benchmark's shape, whole grid in one
-    block): sampled rows of the real Theta against the oracle, FP64 to the
-    kappa floor and the lower orbital precisions to 1e-6."""
+    block): sampled rows of the real Theta against the oracle, FP64 to
+    1e-12 and the lower orbital precisions to 1e-6."""
     c = water64_case
     theta, _, info = isdf.fit(dev(c["d"]["phi"]), None, dev(c["idx"]), prec=prec)
     got = theta[torch.as_tensor(c["rows"]).cuda()].cpu().numpy()
     err = rel(got, c["ref"]["theta"].real)
     print(f"water64 {prec} theta rel err {err:.3e} (kappa {c['kappa']:.2e})")
-    assert err <= (fp64_tol(c["kappa"]) if prec == "fp64" else 1e-6)
+    assert err <= (FP64_THETA if prec == "fp64" else MIXED_THETA)
     assert info["status"] == 0
 
 
@@ -163,10 +171,48 @@ def test_fit_backward_water64_gradient_rows(water64_case, prec):
     phi_sub = np.ascontiguousarray(d["phi"][sub])
     ref = oracle.fit_backward(phi_sub, phi_sub, np.arange(wl.n_mu), g=g[sub])
     err = rel(got, ref["dphi"][wl.n_mu:])
-    tol = max(1e-11, 1e2 * c["kappa"] * EPS) if prec == "fp64" else 1e-5
+    tol = FP64_GRAD if prec == "fp64" else MIXED_GRAD
     print(f"water64 {prec} adjoint rows: dphi {err:.3e} (tol {tol:.1e}, {sample.size} rows)")
     assert err <= tol
     assert info["status"] == 0 and np.isfinite(loss.item()) and loss.item() > 0
+
+
+@pytest.fixture(scope="module")
+def water64_full_adjoint(water64_case):
+    """The oracle's adjoint of the fused loss over the whole 64-water grid
+    (262144 rows; about 100 GB of host memory at its peak), kept only at the
+    interpolation rows and the sampled rows."""
+    c = water64_case
+    d = c["d"]
+    rows = np.concatenate([c["idx"], np.setdiff1d(c["rows"], c["idx"])])
+    ref = oracle.fit_backward(d["phi"], d["phi"], c["idx"], g=d["g"])
+    out = dict(rows=rows, dphi=ref["dphi"][rows].copy(), loss=ref["loss"])
+    del ref
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+def test_fit_backward_water64_interpolation_rows(water64_case, water64_full_adjoint, prec):
+    """Full-size 64-water fused-loss adjoint against the oracle's adjoint over
+    the whole grid: the gradient at all 2048 interpolation points, which
+    carries Mbar = -Theta^H S (the split-K H = G^T diag(g) G over all 262144
+    rows at the split factor this shape selects) and the scatter of
+    Abar^H Phi, and at the sampled other rows; the loss."""
+    c, ref = water64_case, water64_full_adjoint
+    d, wl = c["d"], c["wl"]
+    phi_t, idx_t = dev(d["phi"]), dev(c["idx"])
+    _, minv, _ = isdf.fit(phi_t, None, idx_t, nrows=0, prec=prec)
+    dphi, _, loss, info = isdf.fit_backward(phi_t, None, idx_t, minv, g=dev(d["g"]), prec=prec)
+    got = dphi[torch.as_tensor(ref["rows"]).cuda()].cpu().numpy()
+    del dphi
+    e_idx = rel(got[: wl.n_mu], ref["dphi"][: wl.n_mu])
+    e_all = rel(got, ref["dphi"])
+    e_loss = abs(loss.item() - ref["loss"]) / ref["loss"]
+    tol = FP64_GRAD if prec == "fp64" else MIXED_GRAD
+    print(f"water64 {prec} adjoint: interpolation rows {e_idx:.3e}, with sampled rows {e_all:.3e}, "
+          f"loss {e_loss:.3e} (kappa {c['kappa']:.2e})")
+    assert e_idx <= tol and e_all <= tol and e_loss <= tol
+    assert info["status"] == 0
 
 
 @pytest.fixture(scope="module")
@@ -193,7 +239,9 @@ def test_fit_sio2_shape_sampled_rows(sio2_case):
     phi_t = psi_t[:, : c["wl"].n_phi]
     theta, _, info = isdf.fit(phi_t, psi_t, dev(c["idx"]), rblock=65536)
     got = theta[torch.as_tensor(c["rows"]).cuda()].cpu().numpy()
-    assert rel(got, c["ref"]["theta"]) <= fp64_tol(c["kappa"])
+    err = rel(got, c["ref"]["theta"])
+    print(f"sio2 fp64 theta rel err {err:.3e} (kappa {c['kappa']:.2e})")
+    assert err <= FP64_THETA
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6", "fp16x3"])
@@ -220,7 +268,7 @@ def test_fit_backward_sio2_gradient_rows(sio2_case, prec):
     phi_sub = np.ascontiguousarray(d["phi"][sub])
     psi_sub = np.ascontiguousarray(d["psi"][sub])
     ref = oracle.fit_backward(phi_sub, psi_sub, np.arange(wl.n_mu), g=g[sub])
-    tol = max(1e-11, 1e2 * c["kappa"] * EPS) if prec == "fp64" else 1e-5
+    tol = FP64_GRAD if prec == "fp64" else MIXED_GRAD
     e_phi = rel(got_phi, ref["dphi"][wl.n_mu:])
     e_psi = rel(got_psi, ref["dpsi"][wl.n_mu:])
     print(f"sio2 {prec} adjoint rows: dphi {e_phi:.3e}, dpsi {e_psi:.3e} (tol {tol:.1e}, {sample.size} rows)")
@@ -252,7 +300,7 @@ def test_fit_sio2_mixed_precision_sampled_rows(sio2_case, prec, dtype):
         ref2 = oracle.fit(up[:, : wl.n_phi], up, c["idx"], rows=c["rows"])
         err = rel(got, ref2["theta"])
         print(f"sio2 {prec} c64 theta rel err {err:.3e} vs upcast oracle, {err_i:.3e} vs c128 oracle")
-    assert err <= 1e-6
+    assert err <= MIXED_THETA
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -265,7 +313,9 @@ def test_fit_fp32_gram_water8(water8_fit, dtype):
     th = theta.cpu().numpy().astype(np.float64)
     ref = f["ref"]["theta"].real if dtype == "c128" else \
         oracle.fit_theta(phi.astype(np.complex128), phi.astype(np.complex128), f["idx"]).real
-    assert rel(th, ref) <= 1e-5
+    err = rel(th, ref)
+    print(f"water8 fp32 {dtype} theta rel err {err:.3e}")
+    assert err <= MIXED_THETA
 
 
 def test_fit_duplicate_and_out_of_range_idx():
@@ -308,7 +358,9 @@ def test_minv_ragged_orders(n_mu, aliased):
     assert info["status"] == 0
     th = theta.cpu().numpy()
     want = ref["theta"].real if aliased else ref["theta"]
-    assert rel(th, want) <= fp64_tol(kappa)
+    err = rel(th, want)
+    print(f"minv order {n_mu} aliased {aliased}: theta rel err {err:.3e} (kappa {kappa:.2e})")
+    assert err <= FP64_THETA
     n1 = n_mu if aliased else 2 * n_mu
     W = minv.cpu().numpy().reshape(n1, n1)
     M = ref["M"]
@@ -336,7 +388,7 @@ def test_fit_split_precision_water8(water8_fit, prec, dtype):
         oracle.fit_theta(phi.astype(np.complex128), phi.astype(np.complex128), f["idx"]).real
     err = rel(th, ref)
     print(f"{prec} {dtype} theta rel err {err:.3e}")
-    assert err <= 1e-6
+    assert err <= MIXED_THETA
 
 
 @pytest.mark.parametrize("prec", ["bf16x6", "fp16x3", "fp32"])
@@ -348,7 +400,7 @@ def test_fit_split_precision_complex_ragged(prec):
     kappa = oracle.cc_condition(big[:, :7], big[:, 7:16], idx)
     err = rel(theta.cpu().numpy(), ref["theta"])
     print(f"{prec} complex theta rel err {err:.3e} (kappa {kappa:.1e})")
-    assert err <= max(1e-6, 1e-8 * kappa)
+    assert err <= MIXED_THETA
 
 
 @pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
@@ -375,4 +427,4 @@ def test_zc_split_precision(prec):
     A, B = oracle.gram_blocks(phi, psi, idx)
     ref = oracle.hadamard(A, B)
     got = G.cpu().numpy().view(np.complex128)
-    assert rel(got, ref) <= 1e-6
+    assert rel(got, ref) <= MIXED_THETA

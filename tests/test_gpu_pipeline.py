@@ -11,7 +11,11 @@ pytestmark = pytest.mark.gpu
 isdf = pytest.importorskip("paper_2208_07731_amd")
 from paper_2208_07731_amd.pipeline import ISDFStep  # noqa: E402
 
-EPS = np.finfo(np.float64).eps
+# Parity bars (relative Frobenius norm against the FP64 oracle): FP64 Theta
+# 1e-12 and gradients 1e-11 (kappa of C C^H printed as a diagnostic only);
+# orbital contractions in a split precision: Theta 1e-6, gradients 1e-5.
+FP64_THETA, FP64_GRAD = 1e-12, 1e-11
+MIXED_THETA, MIXED_GRAD = 1e-6, 1e-5
 
 
 def dev(x):
@@ -43,9 +47,11 @@ def test_step_matches_oracle(water8_step):
     th = oracle.fit_theta(s["phi"], s["phi"], km["idx"]).real
     kappa = oracle.cc_condition(s["phi"], s["phi"], km["idx"])
     got = st.theta.cpu().numpy()
-    assert np.linalg.norm(got - th) / np.linalg.norm(th) <= max(1e-12, 4 * kappa * EPS)
+    err_t = np.linalg.norm(got - th) / np.linalg.norm(th)
     dphi = st.dphi.cpu().numpy()
-    assert np.linalg.norm(dphi - ref["dphi"]) / np.linalg.norm(ref["dphi"]) <= max(1e-11, 100 * kappa * EPS)
+    err_g = np.linalg.norm(dphi - ref["dphi"]) / np.linalg.norm(ref["dphi"])
+    print(f"water8 step: theta {err_t:.3e}, dphi {err_g:.3e} (kappa {kappa:.2e})")
+    assert err_t <= FP64_THETA and err_g <= FP64_GRAD
     assert abs(st.loss.item() - ref["loss"]) <= 1e-10 * ref["loss"]
 
 
@@ -149,15 +155,13 @@ def test_saved_gram_adjoint_bitwise(prec, dtype, general):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x6"])
-def test_water64_step_as_benchmarked(prec):
-    """The benchmark's step at full size (64-water: 50 K-means rounds, fit
-    with the Gram blocks kept, fused-loss adjoint from them, one block):
-    with the points it chose, sampled rows of Theta and of dPhi against the
-    oracle (the gradient rows on the sub-problem of the interpolation rows
-    plus the sampled ones)."""
-    import synth
-
-    d = synth.make_workload("water64")
+def test_water64_step_as_benchmarked(full_kmeans_ref, prec):
+    """The 64-water step at full size (50 K-means rounds, fit with the Gram
+    blocks kept, fused-loss adjoint from them, one block): the points it
+    chose equal the oracle's 50-round K-means; sampled rows of Theta and of
+    dPhi against the oracle (the gradient rows on the sub-problem of the
+    interpolation rows plus the sampled ones)."""
+    d, km = full_kmeans_ref("water64")
     wl = d["wl"]
     phi, g = d["phi"], d["g"]
     st = ISDFStep(dev(phi), None, wl.n_mu, d["c0"], wl.kmeans_iters, g=dev(g), prec=prec)
@@ -165,7 +169,8 @@ def test_water64_step_as_benchmarked(prec):
     st.enqueue()
     info = st.check()
     idx = st.idx.cpu().numpy()
-    assert idx.min() >= 0 and len(np.unique(idx)) == wl.n_mu
+    assert np.array_equal(idx, km["idx"])
+    assert info["kmeans"]["iters"] == km["iters"]
     rng = np.random.default_rng(64)
     rows = np.sort(rng.choice(wl.n_r, 256, replace=False))
     kappa = oracle.cc_condition(phi, phi, idx)
@@ -181,8 +186,7 @@ def test_water64_step_as_benchmarked(prec):
     err_g = np.linalg.norm(gotb - want) / np.linalg.norm(want)
     print(f"water64 step {prec}: theta {err_t:.3e}, dphi rows {err_g:.3e} (kappa {kappa:.2e})")
     if prec == "fp64":
-        assert err_t <= max(1e-12, 4 * kappa * EPS)
-        assert err_g <= max(1e-11, 1e2 * kappa * EPS)
+        assert err_t <= FP64_THETA and err_g <= FP64_GRAD
     else:
-        assert err_t <= 1e-6 and err_g <= 1e-5
+        assert err_t <= MIXED_THETA and err_g <= MIXED_GRAD
     assert info["backward"]["status"] == 0 and np.isfinite(st.loss.item())

@@ -231,6 +231,56 @@ def test_hadamard_identity_explicit_z():
     assert np.max(np.abs(zc - G)) <= 1e-13 * np.max(np.abs(G))
 
 
+def test_cc_condition_closed_forms():
+    """kappa_2(C C^H) (Sec. 2.4's matrix) in closed form.
+    (i) Rows at the points are scaled unit vectors a_mu e_mu, Psi = Phi:
+        A(r_mu, r_nu) = a_mu^2 delta, C C^H = diag(a_mu^4), kappa = max/min.
+    (ii) Two points, Phi = Psi, rows e_1 and (cos t, sin t): C C^H =
+        [[1, cos^2 t], [cos^2 t, 1]], kappa = (1 + cos^2 t) / (1 - cos^2 t).
+    (iii) Two points, complex Psi != Phi with rows e_1, (i cos u, sin u):
+        off-diagonal cos t * i cos u, kappa = (1 + cos t cos u) / (1 - cos t cos u)."""
+    rng = np.random.default_rng(71)
+    a = np.array([0.5, 1.0, 1.7, 2.0, 0.9])
+    phi = crandn(rng, 40, 5)
+    idx = np.array([3, 11, 19, 27, 35])
+    phi[idx] = np.diag(a)
+    assert abs(oracle.cc_condition(phi, phi, idx) - (a.max() / a.min()) ** 4) <= 1e-13 * (a.max() / a.min()) ** 4
+    t, u = np.pi / 3, np.pi / 5
+    phi = crandn(rng, 9, 2)
+    psi = crandn(rng, 9, 2)
+    idx = np.array([2, 6])
+    phi[2], phi[6] = [1.0, 0.0], [np.cos(t), np.sin(t)]
+    want = (1 + np.cos(t) ** 2) / (1 - np.cos(t) ** 2)
+    assert abs(oracle.cc_condition(phi, phi, idx) - want) <= 1e-14 * want
+    psi[2], psi[6] = [1.0, 0.0], [1j * np.cos(u), np.sin(u)]
+    cc = np.cos(t) * np.cos(u)
+    want = (1 + cc) / (1 - cc)
+    assert abs(oracle.cc_condition(phi, psi, idx) - want) <= 1e-14 * want
+
+
+def test_cc_condition_against_explicit_c_and_lapack():
+    """kappa_2(C C^H) equals (s_max / s_min)^2 of the singular values of C
+    taken from explicit Z (Sec. 2.1: C = rows of Z at the points), complex and
+    Psi = Phi; for a diagonal C C^H it also equals LAPACK's 1-norm estimate
+    (pocon, exact for diagonal matrices)."""
+    for seed, aliased in ((72, False), (73, True)):
+        phi, psi, idx = tiny_case(seed, n_r=50, n_phi=4, n_psi=5, n_mu=9)
+        if aliased:
+            psi = phi
+        C = oracle.explicit_z(phi, psi)[idx]
+        sv = np.linalg.svd(C, compute_uv=False)
+        want = (sv[0] / sv[-1]) ** 2
+        assert abs(oracle.cc_condition(phi, psi, idx) - want) <= 1e-9 * want
+    a = np.array([3.0, 1.0, 0.25, 2.0])
+    phi = np.zeros((10, 4), dtype=complex)
+    idx = np.array([1, 4, 6, 9])
+    phi[idx] = np.diag(a)
+    M = np.diag(a ** 4)
+    rcond, info = sla.lapack.dpocon(np.asfortranarray(np.linalg.cholesky(M).T), np.linalg.norm(M, 1), uplo="U")
+    assert info == 0
+    assert abs(oracle.cc_condition(phi, phi, idx) * rcond - 1.0) <= 1e-12
+
+
 def test_fit_is_least_squares():
     """eq. theta: Theta minimises ||Z - Theta C||_F (library least squares) and
     satisfies the normal equations (Z - Theta C) C^H = 0."""
