@@ -1,5 +1,7 @@
 """GPU parity of isdf_fit (Gram + Hadamard on MFMA, FP64 Cholesky / inverse,
 Theta) against the FP64 oracle, through the C ABI."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -185,7 +187,10 @@ def water64_full_adjoint(water64_case):
     c = water64_case
     d = c["d"]
     rows = np.concatenate([c["idx"], np.setdiff1d(c["rows"], c["idx"])])
+    print("[oracle] 64-water adjoint over the whole grid", flush=True)
+    t0 = time.time()
     ref = oracle.fit_backward(d["phi"], d["phi"], c["idx"], g=d["g"])
+    print(f"[oracle] done in {time.time() - t0:.1f} s", flush=True)
     out = dict(rows=rows, dphi=ref["dphi"][rows].copy(), loss=ref["loss"])
     del ref
     return out
