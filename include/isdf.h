@@ -14,7 +14,7 @@
  * Conventions shared by every call:
  *  - Every pointer is DEVICE memory unless marked (host).  The caller owns
  *    all memory; the library allocates nothing and keeps no state between
- *    calls.
+ *    calls (apart from the static scratch of isdf_kmeans_noalloc).
  *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = default
  *    stream).  The return value reports argument errors found on the host
  *    before anything is enqueued (negative codes; nothing is written).
@@ -49,6 +49,7 @@ typedef enum {
   ISDF_E_WORKSPACE = -2,    /* ws_bytes below the *_workspace query */
   ISDF_E_HIP = -3,          /* a HIP runtime call failed while enqueueing */
   ISDF_E_UNSUPPORTED = -4,  /* valid request outside what the library implements (e.g. a grid axis isdf_poisson cannot transform) */
+  ISDF_E_SCRATCH = -5,      /* request larger than the static scratch of an allocation-free entry point */
   ISDF_E_NOT_PD = 1,        /* device: C C^H not positive definite (see info->pivot) */
   ISDF_E_NONFINITE = 2,     /* device: NaN or Inf in the orbitals / weight */
   ISDF_W_EMPTY_CLUSTER = 3, /* device: a cluster lost all members (idx = -1) */
@@ -138,6 +139,32 @@ int isdf_kmeans(const isdf_grid* grid /* host */, int32_t dt,
                 int32_t* idx, double* centroids, int32_t* labels, double* w,
                 double* objective, isdf_kmeans_info* info,
                 void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * isdf_kmeans for callers that cannot allocate device memory (code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * allocation): the same computation and the same results bit for bit, with
+ * the same arguments except that there is no workspace.  What isdf_kmeans
+ * keeps in the workspace lives in a static 4 MiB device array of the library
+ * instead (one per GPU, held until the process ends); the call allocates and
+ * frees nothing.
+ *   centroids, labels, w   required here (isdf_kmeans may carve them from the
+ *                          workspace when they are NULL)
+ *   stream                 must belong to the current device (else ISDF_E_ARG)
+ * Requests whose scratch (about 24 n_mu + 24 max_iter + N_r / 64 bytes plus
+ * 2 KiB of alignment) exceeds 4 MiB return ISDF_E_SCRATCH before anything
+ * is enqueued.  Every call on a GPU shares that GPU's scratch, and each
+ * call re-initialises what it reads: calls that overlap on one GPU (on
+ * different streams, or from different host threads without ordering) race
+ * and give undefined results; calls ordered on one stream do not.
+ */
+int isdf_kmeans_noalloc(const isdf_grid* grid /* host */, int32_t dt,
+                        const void* phi, int64_t ld_phi, int32_t n_phi,
+                        const void* psi, int64_t ld_psi, int32_t n_psi,
+                        int32_t weight_kind, uint32_t flags, int32_t n_mu,
+                        const double* c0, int32_t max_iter, double near_tie_rel,
+                        int32_t* idx, double* centroids, int32_t* labels, double* w,
+                        double* objective, isdf_kmeans_info* info, void* stream);
 
 /* ------------------------------------------------------------------ fit */
 /* flags of isdf_fit / isdf_fit_backward */

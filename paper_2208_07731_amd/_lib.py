@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libisdf.so")
 
 # status codes
-OK, E_ARG, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
+OK, E_ARG, E_WORKSPACE, E_HIP, E_UNSUPPORTED, E_SCRATCH = 0, -1, -2, -3, -4, -5
 E_NOT_PD, E_NONFINITE, W_EMPTY_CLUSTER, E_BAD_IDX = 1, 2, 3, 4
 C128, C64 = 0, 1
 PRECS = {"fp64": 0, "fp32": 1, "bf16x6": 2, "fp16x3": 3}
@@ -53,6 +53,8 @@ SIGNATURES = {
     "isdf_kmeans_workspace": (_SZ, [_G, _I32, _I32]),
     "isdf_kmeans": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _I32, _U32, _I32, _P, _I32, _D,
                               _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "isdf_kmeans_noalloc": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _I32, _U32, _I32, _P, _I32, _D,
+                                      _P, _P, _P, _P, _P, _P, _P]),
     "isdf_fit_minv_elems": (_SZ, [_I32, _I32]),
     "isdf_fit_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32, C.c_int, _I64]),
     "isdf_fit_backward_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32, C.c_int, _I64]),

@@ -10,6 +10,7 @@ extern "C" const char* isdf_strerror(int status) {
     case ISDF_E_WORKSPACE: return "workspace too small";
     case ISDF_E_HIP: return "HIP runtime error while enqueueing";
     case ISDF_E_UNSUPPORTED: return "unsupported combination of arguments";
+    case ISDF_E_SCRATCH: return "request exceeds the static scratch of the allocation-free entry point";
     case ISDF_E_NOT_PD: return "C C^H is not positive definite";
     case ISDF_E_NONFINITE: return "non-finite value in the input";
     case ISDF_W_EMPTY_CLUSTER: return "a K-means cluster has no member";

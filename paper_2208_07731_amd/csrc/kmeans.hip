@@ -18,6 +18,8 @@
 #include <float.h>
 #include <limits.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace isdf {
@@ -591,12 +593,11 @@ extern "C" size_t isdf_kmeans_workspace(const isdf_grid* grid, int32_t n_mu, int
   return plan_kmeans(nullptr, 0, nr, n_mu, max_iter, assign_blocks(G), true, true, true, true).bytes;
 }
 
-extern "C" int isdf_kmeans(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
-                           int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
-                           int32_t weight_kind, uint32_t flags, int32_t n_mu, const double* c0,
-                           int32_t max_iter, double near_tie_rel, int32_t* idx, double* centroids,
-                           int32_t* labels, double* w, double* objective, isdf_kmeans_info* info,
-                           void* ws, size_t ws_bytes, void* stream) {
+// Host checks shared by both K-means entry points (nothing touches the device).
+static int kmeans_args(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi, int32_t n_phi,
+                       const void* psi, int64_t ld_psi, int32_t n_psi, int32_t weight_kind, uint32_t flags,
+                       int32_t n_mu, const double* c0, int32_t max_iter, double near_tie_rel, const int32_t* idx,
+                       const double* w, const isdf_kmeans_info* info) {
   if (!dtype_valid(dt_in)) return ISDF_E_ARG;
   const isdf_dtype dt = (isdf_dtype)dt_in;
   if (!grid_ok(grid)) return ISDF_E_ARG;
@@ -612,15 +613,17 @@ extern "C" int isdf_kmeans(const isdf_grid* grid, int32_t dt_in, const void* phi
     if (weight_kind < ISDF_W_SSM || weight_kind > ISDF_W_SQM) return ISDF_E_ARG;
     if (!phi || !psi || n_phi <= 0 || n_psi <= 0 || ld_phi < n_phi || ld_psi < n_psi) return ISDF_E_ARG;
   }
-  KmGeom G = make_geom(grid);
-  const int nparts = assign_blocks(G);
-  KmPlan P = plan_kmeans(ws, ws_bytes, nr, n_mu, max_iter, nparts, !centroids, !labels, !w, !objective);
-  if (P.bytes > ws_bytes || !ws) return ISDF_E_WORKSPACE;
-  if (centroids) P.a.cent = centroids;
-  if (labels) P.a.labels = labels;
-  if (w) P.a.w = w;
-  hipStream_t st = (hipStream_t)stream;
+  return ISDF_OK;
+}
 
+// Enqueues the whole K-means on `st` with the plan's arrays (carved from the
+// caller's workspace or from the static scratch).
+static int kmeans_enqueue(const isdf_grid* grid, isdf_dtype dt, const void* phi, int64_t ld_phi, int32_t n_phi,
+                          const void* psi, int64_t ld_psi, int32_t n_psi, int32_t weight_kind, bool wgiven,
+                          int32_t n_mu, const double* c0, int32_t max_iter, double near_tie_rel, int32_t* idx,
+                          double* objective, isdf_kmeans_info* info, const KmGeom& G, int nparts, const KmPlan& P,
+                          hipStream_t st) {
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   // state must be clean before the weight pass can flag non-finite values
   if (!fill<int>((int*)P.a.st, sizeof(KmState) / sizeof(int), 0, st)) return ISDF_E_HIP;
   if (!wgiven) {
@@ -665,4 +668,88 @@ extern "C" int isdf_kmeans(const isdf_grid* grid, int32_t dt_in, const void* phi
   hipLaunchKernelGGL(km_final, dim3(1), dim3(64), 0, st, P.a, nparts, info, objective, max_iter);
   if (!launch_ok()) return ISDF_E_HIP;
   return ISDF_OK;
+}
+
+extern "C" int isdf_kmeans(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
+                           int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
+                           int32_t weight_kind, uint32_t flags, int32_t n_mu, const double* c0,
+                           int32_t max_iter, double near_tie_rel, int32_t* idx, double* centroids,
+                           int32_t* labels, double* w, double* objective, isdf_kmeans_info* info,
+                           void* ws, size_t ws_bytes, void* stream) {
+  ISDF_TRY(kmeans_args(grid, dt_in, phi, ld_phi, n_phi, psi, ld_psi, n_psi, weight_kind, flags, n_mu, c0, max_iter,
+                       near_tie_rel, idx, w, info));
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  KmGeom G = make_geom(grid);
+  const int nparts = assign_blocks(G);
+  KmPlan P = plan_kmeans(ws, ws_bytes, nr, n_mu, max_iter, nparts, !centroids, !labels, !w, !objective);
+  if (P.bytes > ws_bytes || !ws) return ISDF_E_WORKSPACE;
+  if (centroids) P.a.cent = centroids;
+  if (labels) P.a.labels = labels;
+  if (w) P.a.w = w;
+  return kmeans_enqueue(grid, (isdf_dtype)dt_in, phi, ld_phi, n_phi, psi, ld_psi, n_psi, weight_kind,
+                        (flags & ISDF_KM_WEIGHT_GIVEN) != 0, n_mu, c0, max_iter, near_tie_rel, idx, objective, info,
+                        G, nparts, P, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------ allocation-free form
+// isdf_kmeans_noalloc keeps what isdf_kmeans carves from the caller's
+// workspace (the state, per-round counters, per-cluster bounding boxes and
+// objective partials) in this static array instead: one copy per GPU, which
+// the GPU holds until the process ends.  Host code never uses the array's
+// name as an address: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and kept below.
+constexpr size_t KM_SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[KM_SCRATCH_BYTES];
+
+namespace {
+constexpr int KM_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[KM_MAX_DEVICES];  // device address of `scratch` per device (null: not looked up yet)
+
+// Device address of this device's scratch, looked up on the first call on
+// the device.  The stream must belong to the current device.
+int scratch_address(hipStream_t stream, void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return ISDF_E_HIP;
+  if (dev >= KM_MAX_DEVICES) return ISDF_E_UNSUPPORTED;
+  if (stream) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return ISDF_E_HIP;
+    if (sdev != dev) return ISDF_E_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ISDF_E_HIP;
+    g_scratch_at[dev] = p;
+  }
+  *out = g_scratch_at[dev];
+  return ISDF_OK;
+}
+}  // namespace
+
+extern "C" int isdf_kmeans_noalloc(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
+                                   int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
+                                   int32_t weight_kind, uint32_t flags, int32_t n_mu, const double* c0,
+                                   int32_t max_iter, double near_tie_rel, int32_t* idx, double* centroids,
+                                   int32_t* labels, double* w, double* objective, isdf_kmeans_info* info,
+                                   void* stream) {
+  ISDF_TRY(kmeans_args(grid, dt_in, phi, ld_phi, n_phi, psi, ld_psi, n_psi, weight_kind, flags, n_mu, c0, max_iter,
+                       near_tie_rel, idx, w, info));
+  if (!centroids || !labels || !w) return ISDF_E_ARG;  // outputs the workspace form may carve
+  const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  KmGeom G = make_geom(grid);
+  const int nparts = assign_blocks(G);
+  if (plan_kmeans(nullptr, 0, nr, n_mu, max_iter, nparts, false, false, false, false).bytes > KM_SCRATCH_BYTES)
+    return ISDF_E_SCRATCH;
+  hipStream_t st = (hipStream_t)stream;
+  void* base = nullptr;
+  ISDF_TRY(scratch_address(st, &base));
+  KmPlan P = plan_kmeans(base, KM_SCRATCH_BYTES, nr, n_mu, max_iter, nparts, false, false, false, false);
+  P.a.cent = centroids;
+  P.a.labels = labels;
+  P.a.w = w;
+  return kmeans_enqueue(grid, (isdf_dtype)dt_in, phi, ld_phi, n_phi, psi, ld_psi, n_psi, weight_kind,
+                        (flags & ISDF_KM_WEIGHT_GIVEN) != 0, n_mu, c0, max_iter, near_tie_rel, idx, objective, info,
+                        G, nparts, P, st);
 }

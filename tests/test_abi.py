@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_strerror_and_version():
     lib = L.load()
     assert b"gfx950" in lib.isdf_version()
-    for code in (L.OK, L.E_ARG, L.E_WORKSPACE, L.E_HIP, L.E_UNSUPPORTED, L.E_NOT_PD, L.E_NONFINITE,
+    for code in (L.OK, L.E_ARG, L.E_WORKSPACE, L.E_HIP, L.E_UNSUPPORTED, L.E_SCRATCH, L.E_NOT_PD, L.E_NONFINITE,
                  L.W_EMPTY_CLUSTER, L.E_BAD_IDX):
         assert L.strerror(code) != "unknown status"
     assert L.strerror(12345) == "unknown status"
@@ -88,6 +88,34 @@ def test_kmeans_rejects_bad_arguments(case):
                            kw["kind"], kw["flags"], kw["n_mu"], kw["c0"], kw["iters"], 1e-6, kw["idx"], None, None,
                            None, None, kw["info"], kw["ws"], kw["wsb"], None)
     assert code == (L.E_WORKSPACE if case == "no_ws" else L.E_ARG)
+
+
+@pytest.mark.parametrize("case", ["n_mu0", "null_c0", "bad_kind", "no_labels", "no_w", "no_centroids",
+                                  "beyond_scratch"])
+def test_kmeans_noalloc_rejects_on_the_host(case):
+    """The allocation-free K-means checks its arguments, and that its scratch
+    (4 MiB) holds the request, before touching the device."""
+    lib = L.load()
+    g = L.make_grid(8)
+    kw = dict(kind=0, n_mu=5, c0=FAKE, cent=FAKE, labels=FAKE, w=FAKE, iters=3)
+    if case == "n_mu0":
+        kw["n_mu"] = 0
+    elif case == "null_c0":
+        kw["c0"] = None
+    elif case == "bad_kind":
+        kw["kind"] = 9
+    elif case == "no_labels":
+        kw["labels"] = None
+    elif case == "no_w":
+        kw["w"] = None
+    elif case == "no_centroids":
+        kw["cent"] = None
+    elif case == "beyond_scratch":
+        g = L.make_grid(64)
+        kw["n_mu"] = 200000  # 4.8 MB of per-cluster bounding boxes alone
+    code = lib.isdf_kmeans_noalloc(C.byref(g), L.C128, FAKE, 4, 4, FAKE, 4, 4, kw["kind"], 0, kw["n_mu"], kw["c0"],
+                                   kw["iters"], 1e-6, FAKE, kw["cent"], kw["labels"], kw["w"], None, FAKE, None)
+    assert code == (L.E_SCRATCH if case == "beyond_scratch" else L.E_ARG)
 
 
 @pytest.mark.parametrize("case", ["rows", "ld_theta", "prec_dtype", "null_minv", "flags", "no_ws", "bad_prec"])
