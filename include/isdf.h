@@ -312,6 +312,51 @@ int isdf_fit_backward_gram(const isdf_grid* grid /* host */, int32_t dt,
                            double* loss, int64_t rblock, double* G, double* A, double* B,
                            isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* flags of isdf_fit_backward_rows */
+#define ISDF_BWD_FIRST 1u /* this call starts the sweep (state, packed rows, accumulators) */
+#define ISDF_BWD_LAST 2u  /* this call ends it (interpolation-row terms, info, loss) */
+
+/*
+ * isdf_fit_backward_gram streamed over consecutive row blocks, for a forward
+ * that runs block by block (isdf_zc_ab, then isdf_apply_minv, on rows
+ * [row0, row0 + nrows)): each call takes that block's Gram rows G, A (and B)
+ * right after the forward wrote them, so the Gram products are computed once
+ * per step and only one block of G, A, B is ever held.  Same adjoint as
+ * isdf_fit_backward (reverse mode of eq. theta, interpolation points fixed).
+ *   row0, nrows   the block: rows [row0, row0 + nrows) of the grid
+ *   rblock        the same value in every call of a sweep, >= nrows of each
+ *                 call; the workspace is isdf_fit_backward_gram_workspace
+ *                 with this rblock, and it carries the sweep's state
+ *                 (accumulators of Theta^H S, Abar^H Phi, the loss) from call
+ *                 to call
+ *   G, A, B       the block's rows as isdf_zc_ab wrote them ([nrows][n'],
+ *                 [nrows][2 n_mu]); consumed (overwritten in place)
+ *   theta_bar     NULL (fused loss with field g) or the block's rows of the
+ *                 upstream gradient ([nrows][ld_tbar]); the same choice in
+ *                 every call of a sweep
+ *   g             [N_r] loss field of the whole grid (fused loss)
+ *   dphi, dpsi    [N_r][ld] of the whole grid: each call writes its block's
+ *                 rows; the call with ISDF_BWD_LAST adds the terms at the
+ *                 interpolation rows
+ *   flags         ISDF_BWD_FIRST on the first block, ISDF_BWD_LAST on the last
+ *                 (both for a single block)
+ *   loss, info    written by the ISDF_BWD_LAST call
+ * The blocks of a sweep must cover the grid once, in increasing row order,
+ * on one stream.  With blocks of rblock rows (the last one ragged) the
+ * gradients and the loss are bitwise those of isdf_fit_backward_gram with
+ * the same rblock.
+ */
+int isdf_fit_backward_rows(const isdf_grid* grid /* host */, int32_t dt,
+                           const void* phi, int64_t ld_phi, int32_t n_phi,
+                           const void* psi, int64_t ld_psi, int32_t n_psi,
+                           const int32_t* idx, int32_t n_mu, int32_t prec,
+                           const double* minv,
+                           const void* theta_bar, int64_t ld_tbar, const double* g,
+                           void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi,
+                           double* loss, int64_t row0, int64_t nrows, int64_t rblock,
+                           double* G, double* A, double* B, uint32_t flags,
+                           isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream);
+
 /* ----------------------------------------------------------- residuals */
 /*
  * Least-squares residual of the fit without forming Z (follows from

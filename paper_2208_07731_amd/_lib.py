@@ -20,6 +20,7 @@ PRECS = {"fp64": 0, "fp32": 1, "bf16x6": 2, "fp16x3": 3}
 WEIGHTS = {"ssm": 0, "psm": 1, "sm": 2, "scm": 3, "sqm": 4}
 KM_WEIGHT_GIVEN = 1
 FIT_FACTOR = 1
+BWD_FIRST, BWD_LAST = 1, 2
 
 
 class Grid(C.Structure):
@@ -71,6 +72,9 @@ SIGNATURES = {
     "isdf_fit_backward_gram_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32, C.c_int, _I64]),
     "isdf_fit_backward_gram": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _P,
                                          _P, _I64, _P, _P, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
+    "isdf_fit_backward_rows": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _P,
+                                         _P, _I64, _P, _P, _I64, _P, _I64, _P, _I64, _I64, _I64, _P, _P, _P, _U32,
+                                         _P, _P, _SZ, _P]),
     "isdf_fit_residual_workspace": (_SZ, [_G, _I32, _I32, _I32, _I32, C.c_int, _I64]),
     "isdf_fit_residual": (C.c_int, [_G, C.c_int, _P, _I64, _I32, _P, _I64, _I32, _P, _I32, C.c_int, _P, _I64, _P,
                                     _P, _P, _SZ, _P]),

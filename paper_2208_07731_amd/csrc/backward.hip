@@ -417,8 +417,8 @@ static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec
 template <int PREC, class TS>
 static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const void* fplanes,
                           const TS* X, int64_t ld_x, int n, TS* dX, int64_t ld_dx, int64_t r, int rows, double* Q,
-                          double* Qpart, const double* scales, const AdjPlanes& ap, int sp, const int* ab,
-                          hipStream_t s) {
+                          double* Qpart, const double* scales, const AdjPlanes& ap, int sp, bool first,
+                          const int* ab, hipStream_t s) {
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s))
     return false;
@@ -426,7 +426,7 @@ static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC
   if (!tgemm<typename Prec<PREC>::Q, XC, XC>((int)two_mu, 2 * n, rows, Abar, two_mu, X + 2 * r * ld_x, 2 * ld_x,
                                              Qpart, 2 * (int64_t)n, 1.0, 0.0, ab, s, sp, qn))
     return false;
-  hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(qn)), dim3(256), 0, s, Q, Qpart, qn, sp, r > 0 ? 1 : 0, ab);
+  hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(qn)), dim3(256), 0, s, Q, Qpart, qn, sp, first ? 0 : 1, ab);
   return launch_ok();
 }
 
@@ -447,59 +447,70 @@ static bool orbital_fix(const double* dAbar, int n_mu, const typename Prec<PREC>
   return launch_ok();
 }
 
+// Phases of one adjoint call: BWD_BEGIN sets up (state, index check, packed
+// right-hand sides, (C C^H)^-2) and starts the reductions, BWD_END applies the
+// Mbar terms at the interpolation rows and writes info; the rows
+// [row_lo, row_hi) in between are processed rblock at a time.  G, A, B (and
+// theta_bar) rows are read from Gs + (r - gbase) n1 etc. when given (kept
+// from the forward), else recomputed into the workspace.
+enum { BWD_BEGIN = 1, BWD_END = 2 };
+
 template <int PREC, class TS, class TT>
 static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
                    bool aliased, const int32_t* idx, int n_mu, const double* minv, const TT* tbar, int64_t ld_tbar,
                    const double* g, TS* dphi, int64_t ld_dphi, TS* dpsi, int64_t ld_dpsi, double* loss,
                    int64_t rblock, double* Gs, double* As, double* Bs, isdf_fit_info* info, const BwdPlan& P,
-                   hipStream_t s) {
+                   int64_t row_lo, int64_t row_hi, int64_t gbase, unsigned phases, hipStream_t s) {
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   const int n1 = aliased ? n_mu : 2 * n_mu;
   const int* ab = &P.st->abort;
   typedef typename Prec<PREC>::E T;
-  hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
-  // interpolation indices must be distinct grid points: every launch that
-  // reads or writes rows through idx is a no-op once check_idx has aborted
-  // the call, and fit_finish reports ISDF_E_BAD_IDX
-  if (!fill<int>(P.marker, nr, 0, s)) return ISDF_E_HIP;
-  hipLaunchKernelGGL(check_idx, dim3((unsigned)ceil_div(n_mu, 256)), dim3(256), 0, s, idx, n_mu, nr, P.marker, P.st);
   T *Ephi = (T*)P.Ephi, *Fphi = (T*)P.Fphi, *Xphi = (T*)P.Xphi;
   T *Epsi = aliased ? Ephi : (T*)P.Epsi, *Fpsi = aliased ? Fphi : (T*)P.Fpsi, *Xpsi = aliased ? Xphi : (T*)P.Xpsi;
-  if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
-  hipLaunchKernelGGL((pack_adj_rhs<TS, T>), dim3(blocks_for((int64_t)4 * n_phi * n_mu)), dim3(256), 0, s, phi,
-                     ld_phi, n_phi, idx, n_mu, nr, Fphi);
-  hipLaunchKernelGGL((gather_rows<TS, T>), dim3(blocks_for((int64_t)2 * n_phi * n_mu)), dim3(256), 0, s, phi,
-                     ld_phi, n_phi, idx, n_mu, nr, Xphi);
-  if (!aliased) {
-    if (!pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
-    hipLaunchKernelGGL((pack_adj_rhs<TS, T>), dim3(blocks_for((int64_t)4 * n_psi * n_mu)), dim3(256), 0, s, psi,
-                       ld_psi, n_psi, idx, n_mu, nr, Fpsi);
-    hipLaunchKernelGGL((gather_rows<TS, T>), dim3(blocks_for((int64_t)2 * n_psi * n_mu)), dim3(256), 0, s, psi,
-                       ld_psi, n_psi, idx, n_mu, nr, Xpsi);
-  }
-  if (!launch_ok()) return ISDF_E_HIP;
-  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
-  if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
-    return ISDF_E_HIP;
-  if constexpr (Prec<PREC>::SPLIT >= 0) {  // F planes, scaled like the orbitals (sc[1], sc[3])
-    constexpr int SPLIT = Prec<PREC>::SPLIT;
-    const double* sc = SPLIT == SPLIT_FP16X3 ? P.sc : nullptr;
-    if (!split_rows<SPLIT, double>((const double*)Fphi, n_mu, n_mu, nullptr, 2 * n_phi, 0, 2 * n_phi, P.ap.f_phi,
-                                   P.ap.ldp, 2 * n_phi, sc ? sc + 1 : nullptr, s))
+  if (phases & BWD_BEGIN) {
+    hipLaunchKernelGGL(fit_state_init, dim3(1), dim3(1), 0, s, P.st);
+    // interpolation indices must be distinct grid points: every launch that
+    // reads or writes rows through idx is a no-op once check_idx has aborted
+    // the call, and fit_finish reports ISDF_E_BAD_IDX
+    if (!fill<int>(P.marker, nr, 0, s)) return ISDF_E_HIP;
+    hipLaunchKernelGGL(check_idx, dim3((unsigned)ceil_div(n_mu, 256)), dim3(256), 0, s, idx, n_mu, nr, P.marker, P.st);
+    if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
+    hipLaunchKernelGGL((pack_adj_rhs<TS, T>), dim3(blocks_for((int64_t)4 * n_phi * n_mu)), dim3(256), 0, s, phi,
+                       ld_phi, n_phi, idx, n_mu, nr, Fphi);
+    hipLaunchKernelGGL((gather_rows<TS, T>), dim3(blocks_for((int64_t)2 * n_phi * n_mu)), dim3(256), 0, s, phi,
+                       ld_phi, n_phi, idx, n_mu, nr, Xphi);
+    if (!aliased) {
+      if (!pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
+      hipLaunchKernelGGL((pack_adj_rhs<TS, T>), dim3(blocks_for((int64_t)4 * n_psi * n_mu)), dim3(256), 0, s, psi,
+                         ld_psi, n_psi, idx, n_mu, nr, Fpsi);
+      hipLaunchKernelGGL((gather_rows<TS, T>), dim3(blocks_for((int64_t)2 * n_psi * n_mu)), dim3(256), 0, s, psi,
+                         ld_psi, n_psi, idx, n_mu, nr, Xpsi);
+    }
+    if (!launch_ok()) return ISDF_E_HIP;
+    if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
+    if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
       return ISDF_E_HIP;
-    if (!aliased && !split_rows<SPLIT, double>((const double*)Fpsi, n_mu, n_mu, nullptr, 2 * n_psi, 0, 2 * n_psi,
-                                               P.ap.f_psi, P.ap.ldp, 2 * n_psi, sc ? sc + 3 : nullptr, s))
-      return ISDF_E_HIP;
-  }
-  if (!tbar && !dgemm<KC, KC, double>(n1, n1, n1, minv, n1, minv, n1, P.W2, n1, 1.0, 0.0, 0, ab, s))
-    return ISDF_E_HIP;  // (C C^H)^-2
-  for (int64_t r = 0; r < nr; r += rblock) {
-    const int rows = (int)(nr - r < rblock ? nr - r : rblock);
+    if constexpr (Prec<PREC>::SPLIT >= 0) {  // F planes, scaled like the orbitals (sc[1], sc[3])
+      constexpr int SPLIT = Prec<PREC>::SPLIT;
+      const double* sc = SPLIT == SPLIT_FP16X3 ? P.sc : nullptr;
+      if (!split_rows<SPLIT, double>((const double*)Fphi, n_mu, n_mu, nullptr, 2 * n_phi, 0, 2 * n_phi, P.ap.f_phi,
+                                     P.ap.ldp, 2 * n_phi, sc ? sc + 1 : nullptr, s))
+        return ISDF_E_HIP;
+      if (!aliased && !split_rows<SPLIT, double>((const double*)Fpsi, n_mu, n_mu, nullptr, 2 * n_psi, 0, 2 * n_psi,
+                                                 P.ap.f_psi, P.ap.ldp, 2 * n_psi, sc ? sc + 3 : nullptr, s))
+        return ISDF_E_HIP;
+    }
+    if (!tbar && !dgemm<KC, KC, double>(n1, n1, n1, minv, n1, minv, n1, P.W2, n1, 1.0, 0.0, 0, ab, s))
+      return ISDF_E_HIP;  // (C C^H)^-2
+  }  // BWD_BEGIN
+  for (int64_t r = row_lo; r < row_hi; r += rblock) {
+    const int rows = (int)(row_hi - r < rblock ? row_hi - r : rblock);
+    const bool first = (phases & BWD_BEGIN) && r == row_lo;  // the reductions start here
     // Gram blocks of the r-block: A (and B) kept, G for Theta; saved by the
     // forward (isdf_zc_ab) or recomputed here
-    double* Gb = Gs ? Gs + r * n1 : P.G;
-    double* Ab = As ? As + r * 2 * n_mu : P.A;
-    double* Bb = aliased ? nullptr : (Bs ? Bs + r * 2 * n_mu : P.B);
+    double* Gb = Gs ? Gs + (r - gbase) * n1 : P.G;
+    double* Ab = As ? As + (r - gbase) * 2 * n_mu : P.A;
+    double* Bb = aliased ? nullptr : (Bs ? Bs + (r - gbase) * 2 * n_mu : P.B);
     double* Abar = aliased ? Ab : Bb;  // after the Hadamard step
     double* Bbar = Ab;
     if (!Gs && !gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr,
@@ -513,7 +524,7 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       const int64_t pn = (int64_t)n1 * n1;
       if (!tgemm<double, XC, XC>(n1, n1, rows, Gb, n1, Gb, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
         return ISDF_E_HIP;
-      hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, r > 0 ? 1 : 0,
+      hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, first ? 0 : 1,
                          ab);
       // S = 2 g . (G (C C^H)^-2): Abar / Bbar in place and the loss, in the epilogue
       EpiSAdj epi{Gb, n1, Ab, Bb, 2 * (int64_t)n_mu, g + r, rows, n1, aliased ? 1 : 0, P.lpart};
@@ -528,13 +539,14 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       // Theta = G M^-1, S = Thetabar M^-1 (over G), P += Theta^T S, Abar / Bbar in place
       if (!dgemm<KC, KC, double>(rows, n1, n1, Gb, n1, minv, n1, P.Th, n1, 1.0, 0.0, 0, ab, s)) return ISDF_E_HIP;
       const int64_t ldt = aliased ? ld_tbar : 2 * ld_tbar;
-      if (!dgemm<KC, KC, double, TT>(rows, n1, n1, tbar + r * ldt, ldt, minv, n1, Gb, n1, 1.0, 0.0, 0, ab, s))
+      if (!dgemm<KC, KC, double, TT>(rows, n1, n1, tbar + (r - gbase) * ldt, ldt, minv, n1, Gb, n1, 1.0, 0.0, 0, ab,
+                                     s))
         return ISDF_E_HIP;
       const int sp = sp_phi.h;
       const int64_t pn = (int64_t)n1 * n1;
       if (!tgemm<double, XC, XC>(n1, n1, rows, P.Th, n1, Gb, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn))
         return ISDF_E_HIP;
-      hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, r > 0 ? 1 : 0,
+      hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, first ? 0 : 1,
                          ab);
       hipLaunchKernelGGL(adj_hadamard, dim3(blocks_for((int64_t)rows * n_mu)), dim3(256), 0, s, (const double*)Gb,
                          Ab, Bb, (int64_t)rows, n_mu, aliased ? 1 : 0);
@@ -548,12 +560,13 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                          aliased ? 0 : 1);
     }
     if (!orbital_block<PREC, TS>(Abar, n_mu, Fphi, P.ap.f_phi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi,
-                                 P.Qpart, P.sc + 4, P.ap, sp_phi.q, ab, s))
+                                 P.Qpart, P.sc + 4, P.ap, sp_phi.q, first, ab, s))
       return ISDF_E_HIP;
     if (!aliased && !orbital_block<PREC, TS>(Bbar, n_mu, Fpsi, P.ap.f_psi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows,
-                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, sp_psi.q, ab, s))
+                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, sp_psi.q, first, ab, s))
       return ISDF_E_HIP;
   }
+  if (!(phases & BWD_END)) return ISDF_OK;
   if (!tbar) {
     // Theta^T S = 2 M^-1 H M^-2 with H = G^T diag(g) G
     const int64_t pn = (int64_t)n1 * n1;
@@ -596,7 +609,8 @@ static int bwd_dispatch(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
                         isdf_prec prec, const double* minv, const void* theta_bar, int64_t ld_tbar, const double* g,
                         void* dphi, int64_t ld_dphi, void* dpsi, int64_t ld_dpsi, double* loss, int64_t rblock,
                         double* Gs, double* As, double* Bs, bool saved, isdf_fit_info* info, void* ws,
-                        size_t ws_bytes, void* stream) {
+                        size_t ws_bytes, void* stream, int64_t row0 = 0, int64_t nrows = -1,
+                        unsigned phases = BWD_BEGIN | BWD_END) {
   int64_t nr = 0;
   if (!fit_args_ok(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, &nr)) return ISDF_E_ARG;
   if (!minv || !info || !dphi || !dpsi || rblock <= 0) return ISDF_E_ARG;
@@ -606,7 +620,9 @@ static int bwd_dispatch(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
   if (prec == ISDF_P_FP64 && dt != ISDF_C128) return ISDF_E_ARG;
   const bool aliased = phi == psi && ld_phi == ld_psi && n_phi == n_psi;
   if (!aliased && dphi == dpsi) return ISDF_E_ARG;
-  if (saved && (!Gs || !As || (!aliased && !Bs))) return ISDF_E_ARG;
+  if (nrows < 0) nrows = nr;  // the whole grid in one call
+  if (row0 < 0 || row0 > nr || nrows > nr - row0) return ISDF_E_ARG;
+  if (saved && nrows > 0 && (!Gs || !As || (!aliased && !Bs))) return ISDF_E_ARG;
   if (!saved) Gs = As = Bs = nullptr;
   if (rblock > nr) rblock = nr;
   BwdPlan P = plan_bwd(ws, ws_bytes, nr, n_mu, n_phi, n_psi, aliased, prec, rblock, device_slots(), saved);
@@ -614,7 +630,8 @@ static int bwd_dispatch(const isdf_grid* grid, isdf_dtype dt, const void* phi, i
   hipStream_t s = (hipStream_t)stream;
 #define ISDF_BWD_ARGS(TS)                                                                                        \
   nr, (const TS*)phi, ld_phi, n_phi, (const TS*)psi, ld_psi, n_psi, aliased, idx, n_mu, minv, (const TS*)theta_bar, \
-      ld_tbar, g, (TS*)dphi, ld_dphi, (TS*)dpsi, ld_dpsi, loss, rblock, Gs, As, Bs, info, P, s
+      ld_tbar, g, (TS*)dphi, ld_dphi, (TS*)dpsi, ld_dpsi, loss, rblock, Gs, As, Bs, info, P, row0, row0 + nrows,      \
+      row0, phases, s
   if (dt == ISDF_C128) {
     switch (prec) {
       case ISDF_P_FP64: return bwd_run<ISDF_P_FP64, double, double>(ISDF_BWD_ARGS(double));
@@ -678,4 +695,23 @@ extern "C" int isdf_fit_backward_gram(const isdf_grid* grid, int32_t dt_in, cons
   const isdf_prec prec = (isdf_prec)prec_in;
   return bwd_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, minv, theta_bar, ld_tbar, g,
                       dphi, ld_dphi, dpsi, ld_dpsi, loss, rblock, G, A, B, true, info, ws, ws_bytes, stream);
+}
+
+extern "C" int isdf_fit_backward_rows(const isdf_grid* grid, int32_t dt_in, const void* phi, int64_t ld_phi,
+                                      int32_t n_phi, const void* psi, int64_t ld_psi, int32_t n_psi,
+                                      const int32_t* idx, int32_t n_mu, int32_t prec_in, const double* minv,
+                                      const void* theta_bar, int64_t ld_tbar, const double* g, void* dphi,
+                                      int64_t ld_dphi, void* dpsi, int64_t ld_dpsi, double* loss, int64_t row0,
+                                      int64_t nrows, int64_t rblock, double* G, double* A, double* B, uint32_t flags,
+                                      isdf_fit_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!dtype_valid(dt_in)) return ISDF_E_ARG;
+  if (!prec_valid(prec_in)) return ISDF_E_ARG;
+  if (flags & ~(ISDF_BWD_FIRST | ISDF_BWD_LAST)) return ISDF_E_ARG;
+  if (nrows < 0 || rblock <= 0) return ISDF_E_ARG;
+  const isdf_dtype dt = (isdf_dtype)dt_in;
+  const isdf_prec prec = (isdf_prec)prec_in;
+  const unsigned phases = ((flags & ISDF_BWD_FIRST) ? BWD_BEGIN : 0u) | ((flags & ISDF_BWD_LAST) ? BWD_END : 0u);
+  return bwd_dispatch(grid, dt, phi, ld_phi, n_phi, psi, ld_psi, n_psi, idx, n_mu, prec, minv, theta_bar, ld_tbar, g,
+                      dphi, ld_dphi, dpsi, ld_dpsi, loss, rblock, G, A, B, true, info, ws, ws_bytes, stream, row0, nrows,
+                      phases);
 }

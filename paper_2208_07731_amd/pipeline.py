@@ -8,10 +8,14 @@ With block_rows < N_r the forward runs Z C^H and Theta block by block
 (block_rows rows at a time); keep_theta=False then keeps only the current
 block of Theta (the streamed form for grids whose Theta does not fit).
 
-When the forward runs as one block, it also keeps the Gram blocks A = Phi
-Phi_mu^H (and B = Psi Psi_mu^H) beside Z C^H (isdf_zc_ab), and the adjoint
-takes them instead of recomputing its Gram products (isdf_fit_backward_gram,
-bitwise the same gradients); save_gram=False recomputes them.
+With the adjoint, each block's forward also keeps the Gram blocks
+A = Phi Phi_mu^H (and B = Psi Psi_mu^H) beside Z C^H (isdf_zc_ab), and the
+adjoint of that block runs right after its Theta from them
+(isdf_fit_backward_rows, blocks in grid order, the last one applying the
+interpolation-row terms), so no Gram product is computed twice and only one
+block of G, A, B and Theta is ever held; save_gram=False instead runs the
+whole adjoint after the forward, recomputing its Gram products in r-blocks
+of `rblock` rows (isdf_fit_backward).
 
 Nothing is allocated and nothing synchronises inside enqueue(): every
 output, workspace and info struct is created in the constructor, and the
@@ -80,14 +84,14 @@ class ISDFStep:
         self.theta = torch.empty(n_r if self.keep_theta else self.block_rows, n_mu,
                                  dtype=real_t if self.aliased else cplx_t, device=dev)
         if save_gram is None:
-            save_gram = backward and len(self.blocks) == 1
-        if save_gram and (not backward or len(self.blocks) != 1):
-            raise ValueError("save_gram needs the adjoint and a single forward block")
+            save_gram = backward
+        if save_gram and not backward:
+            raise ValueError("save_gram needs the adjoint")
         self.save_gram = save_gram
         self.A = self.B = None
         if save_gram:
-            self.A = torch.empty(n_r, 2 * n_mu, dtype=f64, device=dev)
-            self.B = None if self.aliased else torch.empty(n_r, 2 * n_mu, dtype=f64, device=dev)
+            self.A = torch.empty(self.block_rows, 2 * n_mu, dtype=f64, device=dev)
+            self.B = None if self.aliased else torch.empty(self.block_rows, 2 * n_mu, dtype=f64, device=dev)
         if backward:
             if g is None:
                 raise ValueError("the adjoint needs the loss field g")
@@ -96,9 +100,13 @@ class ISDFStep:
             self.dpsi = self.dphi if self.aliased else torch.empty(n_r, self.nps, dtype=psi.dtype, device=dev)
             self.loss = torch.zeros((), dtype=f64, device=dev)
             self.bwd_info = torch.zeros(C.sizeof(L.FitInfo), dtype=u8, device=dev)
-            wsq = self.lib.isdf_fit_backward_gram_workspace if save_gram else self.lib.isdf_fit_backward_workspace
-            self.bwd_ws = torch.empty(wsq(C.byref(self.grid), n_mu, self.npf, self.nps, int(self.aliased), self.prec,
-                                          self.rblock), dtype=u8, device=dev)
+            if save_gram:
+                wsb = self.lib.isdf_fit_backward_gram_workspace(C.byref(self.grid), n_mu, self.npf, self.nps,
+                                                                int(self.aliased), self.prec, self.block_rows)
+            else:
+                wsb = self.lib.isdf_fit_backward_workspace(C.byref(self.grid), n_mu, self.npf, self.nps,
+                                                           int(self.aliased), self.prec, self.rblock)
+            self.bwd_ws = torch.empty(wsb, dtype=u8, device=dev)
 
     @staticmethod
     def _ptr(t):
@@ -111,11 +119,15 @@ class ISDFStep:
     def enqueue(self, block_events=None, phase_events=None, factor_events=None):
         """Enqueue the step on the current stream (the factorisation of C C^H
         forks onto a second stream right after K-means and joins back before
-        the first solve).  block_events (one triple of events per row block)
-        bracket each block's Z C^H and Theta launches; phase_events (5 events)
-        are recorded before K-means and after K-means, the fork, the last
-        Theta block and the adjoint; factor_events (2) bracket the
-        factorisation on its own stream."""
+        the first solve).  block_events (one 4-tuple of events per row block)
+        bracket each block's Z C^H, Theta and (kept Gram blocks) adjoint
+        launches (with kept Gram blocks the adjoint runs block by block between
+        the third and fourth event; otherwise those two coincide);
+        phase_events (5 events) are recorded before K-means, after K-means,
+        after the fork, after the last block, and after the adjoint that
+        follows the blocks when the Gram blocks are recomputed (else right
+        after the fourth); factor_events (2) bracket the factorisation on its
+        own stream."""
         main = torch.cuda.current_stream()
         lib, s = self.lib, main.cuda_stream
         gp = C.byref(self.grid)
@@ -167,15 +179,19 @@ class ISDFStep:
                                            self.n1, nrows, self.dt, th, self.n_mu, s), "isdf_apply_minv")
             if be:
                 be[2].record()
+            if self.backward and self.save_gram:
+                # this block's share of the adjoint, from the Gram blocks just kept
+                flags = (L.BWD_FIRST if b == 0 else 0) | (L.BWD_LAST if b == len(self.blocks) - 1 else 0)
+                self._call(lib.isdf_fit_backward_rows(
+                    gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps, self.idx.data_ptr(),
+                    self.n_mu, self.prec, self.minv.data_ptr(), None, 0, self.g.data_ptr(), self.dphi.data_ptr(),
+                    self.npf, self.dpsi.data_ptr(), self.nps, self.loss.data_ptr(), r0, nrows, self.block_rows,
+                    self.G.data_ptr(), self.A.data_ptr(), self._ptr(self.B), flags, self.bwd_info.data_ptr(),
+                    self.bwd_ws.data_ptr(), self.bwd_ws.numel(), s), "isdf_fit_backward_rows")
+            if be:
+                be[3].record()
         mark(3)
-        if self.backward and self.save_gram:
-            self._call(lib.isdf_fit_backward_gram(
-                gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps, self.idx.data_ptr(), self.n_mu,
-                self.prec, self.minv.data_ptr(), None, 0, self.g.data_ptr(), self.dphi.data_ptr(), self.npf,
-                self.dpsi.data_ptr(), self.nps, self.loss.data_ptr(), self.rblock, self.G.data_ptr(),
-                self.A.data_ptr(), self._ptr(self.B), self.bwd_info.data_ptr(), self.bwd_ws.data_ptr(),
-                self.bwd_ws.numel(), s), "isdf_fit_backward_gram")
-        elif self.backward:
+        if self.backward and not self.save_gram:
             self._call(lib.isdf_fit_backward(gp, self.dt, self.pp, self.lp, self.npf, self.ps, self.lps, self.nps,
                                              self.idx.data_ptr(), self.n_mu, self.prec, self.minv.data_ptr(), None,
                                              0, self.g.data_ptr(), self.dphi.data_ptr(), self.npf,

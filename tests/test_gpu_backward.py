@@ -367,3 +367,104 @@ def test_backward_rejects_bad_interpolation_index(case, kept):
         raw = L.FitInfo.from_buffer_copy(bytes(infob.cpu().numpy()))
         info = {f: getattr(raw, f) for f, _ in L.FitInfo._fields_}
     assert info["status"] == L.E_BAD_IDX and info["bad_idx"] == pos, info
+
+
+@pytest.mark.parametrize("general", [False, True])
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+def test_backward_rows_streamed_equals_one_call(water8, water8_idx, general, fused, prec):
+    """isdf_fit_backward_rows over row blocks of 5000 (8-water orbitals,
+    13824 rows: the last block ragged), each right after isdf_zc_ab wrote
+    that block's Gram rows into a buffer of one block, gives bitwise the
+    gradients and loss of isdf_fit_backward_gram with rblock = 5000 over
+    whole-grid Gram rows; and the oracle's within the FP64 / mixed bars.
+    general: Phi = the first 16 orbitals, Psi = all 32 (complex Theta)."""
+    from paper_2208_07731_amd import _lib as L
+    import ctypes as C
+
+    lib = L.load()
+    rng = np.random.default_rng(33 + general + 2 * fused)
+    full = water8["phi"]
+    nr, n_mu = full.shape[0], len(water8_idx)
+    idx = water8_idx.astype(np.int32)
+    t = dev(full)
+    n_p = 16 if general else 32
+    n_s = 32
+    phi = full[:, :n_p]
+    psi = full if general else phi
+    tp = t[:, :n_p]
+    ts = t
+    shape = (nr, n_mu)
+    tbar = None if fused else (rng.standard_normal(shape) + 1j * rng.standard_normal(shape) if general
+                               else rng.standard_normal(shape))
+    g = synth.loss_field(nr, 1004)
+    idx_t, g_t = dev(idx), dev(g)
+    tb = None if fused else dev(tbar)
+    p = L.PRECS[prec]
+    gr = L.make_grid(water8["wl"].n)
+    s = torch.cuda.current_stream().cuda_stream
+    _, minv, _ = isdf.fit(tp, ts if general else None, idx_t, nrows=0, prec=prec)
+    n1 = 2 * n_mu if general else n_mu
+    R = 5000
+    ld_p, ld_s = tp.stride(0), ts.stride(0)
+    psi_ptr, ld_q, n_q = (ts.data_ptr(), ld_s, n_s) if general else (tp.data_ptr(), ld_p, n_p)
+    zws = torch.empty(lib.isdf_zc_workspace(n_mu, n_p, n_q, int(not general), p, nr), dtype=torch.uint8,
+                      device="cuda")
+    bws = torch.empty(lib.isdf_fit_backward_gram_workspace(C.byref(gr), n_mu, n_p, n_q, int(not general), p, R),
+                      dtype=torch.uint8, device="cuda")
+
+    def grads():
+        dphi = torch.full((nr, n_p), 3.0, dtype=torch.complex128, device="cuda")
+        dpsi = torch.full((nr, n_q), 3.0, dtype=torch.complex128, device="cuda") if general else dphi
+        return dphi, dpsi, torch.zeros((), dtype=torch.float64, device="cuda"), \
+            torch.zeros(C.sizeof(L.FitInfo), dtype=torch.uint8, device="cuda")
+
+    def zc_ab(r0, rows, G, A, B):
+        assert lib.isdf_zc_ab(C.byref(gr), L.C128, tp.data_ptr(), ld_p, n_p, psi_ptr, ld_q, n_q, idx_t.data_ptr(),
+                              n_mu, p, r0, rows, G.data_ptr(), n1, A.data_ptr(), None if B is None else B.data_ptr(),
+                              zws.data_ptr(), zws.numel(), s) == L.OK
+
+    def new_ab(rows):
+        return (torch.empty(rows, n1, dtype=torch.float64, device="cuda"),
+                torch.empty(rows, 2 * n_mu, dtype=torch.float64, device="cuda"),
+                torch.empty(rows, 2 * n_mu, dtype=torch.float64, device="cuda") if general else None)
+
+    # one call over whole-grid Gram rows
+    G, A, B = new_ab(nr)
+    zc_ab(0, nr, G, A, B)
+    ref_phi, ref_psi, ref_loss, info1 = grads()
+    assert lib.isdf_fit_backward_gram(C.byref(gr), L.C128, tp.data_ptr(), ld_p, n_p, psi_ptr, ld_q, n_q,
+                                      idx_t.data_ptr(), n_mu, p, minv.data_ptr(), None if tb is None else tb.data_ptr(),
+                                      n_mu, g_t.data_ptr(), ref_phi.data_ptr(), n_p, ref_psi.data_ptr(), n_q,
+                                      ref_loss.data_ptr(), R, G.data_ptr(), A.data_ptr(),
+                                      None if B is None else B.data_ptr(), info1.data_ptr(), bws.data_ptr(),
+                                      bws.numel(), s) == L.OK
+    del G, A, B
+    # streamed: one block of Gram rows at a time
+    G, A, B = new_ab(R)
+    dphi, dpsi, loss, info2 = grads()
+    blocks = list(range(0, nr, R))
+    for k, r0 in enumerate(blocks):
+        rows = min(R, nr - r0)
+        zc_ab(r0, rows, G, A, B)
+        flags = (L.BWD_FIRST if k == 0 else 0) | (L.BWD_LAST if k == len(blocks) - 1 else 0)
+        tb_ptr = None if tb is None else tb.data_ptr() + r0 * tb.stride(0) * tb.element_size()
+        assert lib.isdf_fit_backward_rows(C.byref(gr), L.C128, tp.data_ptr(), ld_p, n_p, psi_ptr, ld_q, n_q,
+                                          idx_t.data_ptr(), n_mu, p, minv.data_ptr(), tb_ptr, n_mu, g_t.data_ptr(),
+                                          dphi.data_ptr(), n_p, dpsi.data_ptr(), n_q, loss.data_ptr(), r0, rows, R,
+                                          G.data_ptr(), A.data_ptr(), None if B is None else B.data_ptr(), flags,
+                                          info2.data_ptr(), bws.data_ptr(), bws.numel(), s) == L.OK
+    torch.cuda.synchronize()
+    assert len(blocks) == 3 and nr % R != 0
+    assert torch.equal(dphi, ref_phi) and torch.equal(dpsi, ref_psi)
+    assert loss.item() == ref_loss.item()
+    inf = L.FitInfo.from_buffer_copy(bytes(info2.cpu().numpy()))
+    assert inf.status == L.OK
+    ref = oracle.fit_backward(phi, psi, idx, theta_bar=tbar, g=g if fused else None)
+    e_phi = rel(dphi.cpu().numpy(), ref["dphi"])
+    e_psi = rel(dpsi.cpu().numpy(), ref["dpsi"])
+    tol = FP64_GRAD if prec == "fp64" else MIXED_GRAD
+    print(f"streamed adjoint {prec} general={general} fused={fused}: dphi {e_phi:.3e} dpsi {e_psi:.3e}")
+    assert e_phi <= tol and e_psi <= tol
+    if fused:
+        assert abs(loss.item() - ref["loss"]) <= tol * ref["loss"]

@@ -56,13 +56,19 @@ def test_step_matches_oracle(water8_step):
 
 
 def test_streamed_blocks_equal_one_block(water8_step):
-    """Z C^H and Theta in ragged row blocks give Theta bit for bit."""
+    """Z C^H and Theta in ragged row blocks give Theta bit for bit; the
+    adjoint streamed with them (its reductions summed block by block) gives
+    the one-block gradients to FP64 rounding, and bitwise those of the
+    recomputing adjoint with r-blocks of the same size."""
     s = water8_step
     one, _ = run_step(s)
     blk, _ = run_step(s, block_rows=5000)
+    rec, _ = run_step(s, block_rows=5000, rblock=5000, save_gram=False)
     assert len(blk.blocks) == 3
     assert torch.equal(one.theta, blk.theta)
-    assert torch.equal(one.dphi, blk.dphi)
+    a, b = one.dphi.cpu().numpy(), blk.dphi.cpu().numpy()
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) <= 1e-13
+    assert torch.equal(blk.dphi, rec.dphi) and blk.loss.item() == rec.loss.item()
 
 
 def test_graph_replay_matches_eager(water8_step):
@@ -114,7 +120,8 @@ def test_step_general_psi_matches_api():
     assert torch.equal(st.idx, km.idx)
     theta, minv, _ = isdf.fit(phi, psi, km.idx, grid=n)
     assert torch.equal(st.theta, theta)
-    dphi, dpsi, loss, _ = isdf.fit_backward(phi, psi, km.idx, minv, g=g, grid=n, rblock=st.rblock)
+    # the step's adjoint runs block by block with its forward: r-blocks of block_rows
+    dphi, dpsi, loss, _ = isdf.fit_backward(phi, psi, km.idx, minv, g=g, grid=n, rblock=st.block_rows)
     assert torch.equal(st.dphi, dphi) and torch.equal(st.dpsi, dpsi)
     assert st.loss.item() == loss.item()
 
@@ -124,10 +131,10 @@ def test_step_general_psi_matches_api():
                                         ("bf16x6", np.complex64)])
 @pytest.mark.parametrize("general", [False, True])
 def test_saved_gram_adjoint_bitwise(prec, dtype, general):
-    """The adjoint from the forward's Gram blocks (isdf_zc_ab +
-    isdf_fit_backward_gram) gives the recomputing adjoint's gradients and
-    loss bit for bit, with ragged backward r-blocks (rblock = 100), for
-    complex128 and complex64 orbitals."""
+    """The adjoint streamed block by block from the forward's Gram blocks
+    (isdf_zc_ab + isdf_fit_backward_rows, blocks of 100 rows, the last one
+    ragged) gives the recomputing adjoint's gradients and loss (r-blocks of
+    100 rows) bit for bit, for complex128 and complex64 orbitals."""
     rng = np.random.default_rng(92 + general)
     n = (6, 7, 8)
     nr = 336
@@ -139,7 +146,7 @@ def test_saved_gram_adjoint_bitwise(prec, dtype, general):
     c0 = oracle.grid_points(n)[rng.choice(nr, 24, replace=False)]
     out = []
     for save in (True, False):
-        st = ISDFStep(phi, psi, 24, c0, 8, g=g, grid=n, prec=prec, rblock=100, save_gram=save)
+        st = ISDFStep(phi, psi, 24, c0, 8, g=g, grid=n, prec=prec, rblock=100, block_rows=100, save_gram=save)
         assert st.save_gram == save
         st.enqueue()
         st.check()
