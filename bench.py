@@ -87,8 +87,9 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int, saved_gram: bool = Fal
     solve  : 2 N_r n1^2 (FP64).
     adjoint: Gram recompute 8 N_r N_mu N (not when the forward kept the
              Gram blocks), orbital products Abar F and Abar^T X 16 N_r N_mu N,
-             and the fused-loss FP64 products: H = G^T g G over the lower half
-             (N_r n1^2) and S = G M^-2 (2 N_r n1^2).
+             and the fused-loss products H = G^T g G over the lower half
+             (N_r n1^2; in the split precision when the orbital products are)
+             and S = G M^-2 (2 N_r n1^2, FP64).
     """
     n_e = wl.n_phi + (0 if wl.aliased else wl.n_psi)
     esize = 16
@@ -112,11 +113,13 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int, saved_gram: bool = Fal
                      "frac": round(tf * issued / MFMA_PEAK[pk], 4)}
         if issued != 1:
             out[name]["issued_per_flop"] = issued
-    # adjoint: FP64 products with the inverse (H, S) plus orbital products in
-    # the orbital precision; frac = time the two would take at their peaks
-    # over the measured time
-    f64 = 3.0 * wl.n_r * n1 * n1
-    orb = (16.0 if saved_gram else 24.0) * wl.n_r * wl.n_mu * n_e
+    # adjoint: the FP64 product with the inverse (S = G M^-2, 2 N_r n1^2),
+    # H = G^T g G (N_r n1^2: FP64, or the split precision with split orbital
+    # contractions) and the orbital products in the orbital precision; frac =
+    # time the parts would take at their peaks over the measured time
+    split = prec in ("bf16x6", "fp16x3")
+    f64 = (2.0 if split else 3.0) * wl.n_r * n1 * n1
+    orb = (16.0 if saved_gram else 24.0) * wl.n_r * wl.n_mu * n_e + (1.0 * wl.n_r * n1 * n1 if split else 0.0)
     ms = phases["adjoint"]
     t_peak = f64 / (MFMA_PEAK["fp64"] * 1e12) + orb * ISSUED[prec] / (MFMA_PEAK[prec] * 1e12)
     out["adjoint"] = {"ms": ms, "bound": "mfma", "flops": f64 + orb, "fp64_flops": f64, "orbital_flops": orb,

@@ -94,10 +94,11 @@ struct EpiSAdj {
   int M, N;
   int aliased;
   double* partial;
+  double* amax;  // optional [2]: max |re|, |im| of Abar and of Bbar written here (binary16 scales)
   template <class Cfg, class Acc>
   __device__ __forceinline__ void apply(const Acc (&acc)[Cfg::MI][Cfg::NI], const TileAt& at) const {
     __shared__ double red[Cfg::THREADS / ISDF_WAVE];
-    double sl = 0.0;
+    double sl = 0.0, ma = 0.0, mb = 0.0;
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
@@ -115,7 +116,9 @@ struct EpiSAdj {
             if (ok) {
               double2* a = reinterpret_cast<double2*>(A + (int64_t)m * ldab + 2 * n);
               const double2 av = *a;
-              *a = make_double2(s * av.x, s * av.y);
+              const double2 o = make_double2(s * av.x, s * av.y);
+              *a = o;
+              ma = fmax(ma, fmax(fabs(o.x), fabs(o.y)));
             }
           } else {
             const double so = __shfl_xor(s, 1, ISDF_WAVE);
@@ -125,11 +128,15 @@ struct EpiSAdj {
               if (c == 0) {
                 double2* bp = reinterpret_cast<double2*>(B + (int64_t)m * ldab + 2 * nu);
                 const double2 bv = *bp;
-                *bp = make_double2(sr * bv.x - si * bv.y, sr * bv.y + si * bv.x);
+                const double2 o = make_double2(sr * bv.x - si * bv.y, sr * bv.y + si * bv.x);
+                *bp = o;
+                ma = fmax(ma, fmax(fabs(o.x), fabs(o.y)));
               } else {
                 double2* ap = reinterpret_cast<double2*>(A + (int64_t)m * ldab + 2 * nu);
                 const double2 av = *ap;
-                *ap = make_double2(sr * av.x + si * av.y, sr * av.y - si * av.x);
+                const double2 o = make_double2(sr * av.x + si * av.y, sr * av.y - si * av.x);
+                *ap = o;
+                mb = fmax(mb, fmax(fabs(o.x), fabs(o.y)));
               }
             }
           }
@@ -137,6 +144,17 @@ struct EpiSAdj {
       }
     sl = wave_sum(sl);
     if (at.lane == 0) red[threadIdx.x >> 6] = sl;
+    if (amax) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        ma = fmax(ma, __shfl_xor(ma, o, ISDF_WAVE));
+        mb = fmax(mb, __shfl_xor(mb, o, ISDF_WAVE));
+      }
+      if (at.lane == 0) {
+        if (ma > 0.0) atomic_max_pos(amax, ma);
+        if (mb > 0.0) atomic_max_pos(amax + 1, mb);
+      }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0.0;
@@ -145,6 +163,31 @@ struct EpiSAdj {
     }
   }
 };
+
+// Largest |x| and |x rowscale[k]| over the rows of a real r-major block
+// (binary16 scales of the two split operands of H), folded into out[0] and
+// out[1] (positive doubles order like their bit patterns).
+__global__ void absmax_real2(const double* __restrict__ x, int64_t ld, int n, int64_t rows,
+                             const double* __restrict__ rowscale, double* out) {
+  double m = 0.0, mg = 0.0;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const double gr = fabs(rowscale[r]);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      const double v = fabs(x[r * ld + k]);
+      m = fmax(m, v);
+      mg = fmax(mg, v * gr);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m = fmax(m, __shfl_xor(m, o, ISDF_WAVE));
+    mg = fmax(mg, __shfl_xor(mg, o, ISDF_WAVE));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (mg > 0.0) atomic_max_pos(out, mg);
+    if (m > 0.0) atomic_max_pos(out + 1, m);
+  }
+}
 
 // Upper triangle of an n x n matrix from its lower triangle.
 __global__ void mirror_lower(double* __restrict__ H, int n, const int* abort) {
@@ -242,6 +285,18 @@ __global__ void copy_rows(TS* __restrict__ dst, int64_t ldd, const TS* __restric
   }
 }
 
+// K extent of the transposed planes of a block of `rows` grid rows.
+static inline int ldk_of(int64_t rows) { return (int)ceil_div(rows, 32) * 32; }
+
+// Split factor of a split-engine product with `tiles` output tiles (128 x 64)
+// contracted over K grid rows: 1, or enough K slices of at least 4096 rows
+// to give every workgroup slot a tile.
+static int split_k_for(int64_t tiles, int64_t K, int slots) {
+  int s = 1;
+  while (s < MAX_SPLITS && tiles * s < slots && ceil_div(K, 2 * s) >= 4096) s *= 2;
+  return s;
+}
+
 static unsigned blocks_for(int64_t n) {
   int64_t b = ceil_div(n, 256);
   return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
@@ -322,8 +377,10 @@ struct BwdPlan {
   int* marker;   // [N_r] occupancy of the interpolation rows (check_idx)
   void *Ephi, *Epsi, *Fphi, *Fpsi, *Xphi, *Xpsi;
   double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart, *W2;
-  double* amax;  // [4] max |Phi|, |Psi|, |Abar|, |Bbar| (binary16 split)
-  double* sc;    // [12] operand scales: Gram (4), dPhi (2), dPsi (2), padding
+  double* amax;  // [6] max |Phi|, |Psi|, |Abar|, |Bbar|, |g G|, |G| (binary16 split)
+  double* sc;    // [16] operand scales: Gram (4), dPhi (2), dPsi (2), padding (4), H (2), padding (2)
+  void* tp;      // transposed planes of the products over grid rows (H, Abar^T X), split precisions
+  double* tpart; // split-K partials of those products (null: never split)
   SplitWork sw;  // orbital-row and Gram right-hand-side planes (split precisions)
   AdjPlanes ap;  // Abar / Bbar and F planes (split precisions)
   int slots;     // workgroup slots the split factors were chosen for
@@ -351,8 +408,8 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   const int nmax = n_phi > n_psi ? n_phi : n_psi;
   P.st = c.take<FitState>(1);
   P.marker = c.take<int>(nr);
-  P.amax = c.take<double>(4);
-  P.sc = c.take<double>(12);
+  P.amax = c.take<double>(6);
+  P.sc = c.take<double>(16);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
   P.Fphi = c.take<char>((size_t)2 * n_phi * 2 * n_mu * tsize);
   P.Xphi = c.take<char>((size_t)n_mu * 2 * n_phi * tsize);
@@ -382,8 +439,77 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   P.lpart = c.take<double>((size_t)ceil_div(rblock, 128) * ceil_div(n1, 128));
   P.sw = carve_split(c, prec, n_phi, n_psi, aliased, n_mu, rblock > n_mu ? rblock : n_mu);
   P.ap = carve_adj(c, prec, n_phi, n_psi, aliased, n_mu, rblock);
+  if (prec == ISDF_P_BF16X6 || prec == ISDF_P_FP16X3) {
+    // one buffer serves H's two operands and then each orbital set's Abar^T X
+    const int np = prec == ISDF_P_BF16X6 ? 3 : 2;
+    const int64_t cols = 2 * n1 > 2 * (int64_t)n_mu + 2 * nmax ? 2 * n1 : 2 * (int64_t)n_mu + 2 * nmax;
+    P.tp = c.take<char>((size_t)np * cols * ldk_of(rblock) * 2);
+    // split-K partials: the largest split factor over the block sizes that occur
+    const int t1 = (int)ceil_div(n1, 128);
+    const int64_t th = split_tiles(t1, (int)ceil_div(n1, 64), 2, 1);
+    const int64_t tq = ceil_div(2 * (int64_t)n_mu, 128) * ceil_div(2 * (int64_t)nmax, 64);
+    int64_t need = 0;
+    for (int64_t rows : {rblock, nr - (ceil_div(nr, rblock) - 1) * rblock}) {
+      const int sh2 = split_k_for(th, ldk_of(rows), slots), sq2 = split_k_for(tq, ldk_of(rows), slots);
+      if (sh2 > 1 && sh2 * n1 * n1 > need) need = sh2 * n1 * n1;
+      if (sq2 > 1 && sq2 * 2 * (int64_t)n_mu * 2 * nmax > need) need = sq2 * 2 * (int64_t)n_mu * 2 * nmax;
+    }
+    if (need > 0) P.tpart = c.take<double>((size_t)need);
+  }
   P.bytes = c.used;
   return P;
+}
+
+template <int SPLIT>
+static bool split_t(const double* x, int64_t ld, int ncols, int rows, const double* rowscale, void* out, int ldk,
+                    const double* scale, hipStream_t s) {
+  typedef typename SplitT<SPLIT>::P P;
+  dim3 grid((unsigned)ceil_div(ldk, 64), (unsigned)ceil_div(ncols, 64));
+  hipLaunchKernelGGL((split_planes_t<SPLIT, double>), grid, dim3(256), 0, s, x, ld, ncols, rows, rowscale, (P*)out,
+                     ldk, (int64_t)ncols * ldk, scale);
+  return launch_ok();
+}
+template <int SPLIT>
+static bool split_t(const float* x, int64_t ld, int ncols, int rows, const double* rowscale, void* out, int ldk,
+                    const double* scale, hipStream_t s) {
+  typedef typename SplitT<SPLIT>::P P;
+  dim3 grid((unsigned)ceil_div(ldk, 64), (unsigned)ceil_div(ncols, 64));
+  hipLaunchKernelGGL((split_planes_t<SPLIT, float>), grid, dim3(256), 0, s, x, ld, ncols, rows, rowscale, (P*)out,
+                     ldk, (int64_t)ncols * ldk, scale);
+  return launch_ok();
+}
+
+// C (=, or += when accumulate) X^T Y over the `rows` grid rows of r-major
+// blocks X [rows][mx] and Y [rows][ny], on 16-bit matrix cores: both split
+// transposed into `tp` (X scaled by rowscale when given; binary16 operand
+// scales sc[0], sc[1]), then one split product, split over K into partial
+// slices (fixed-order reduction) when its tiles alone would not fill the
+// GPU.  lower_only (X = Y up to rowscale, mx = ny): the lower tiles only.
+template <int SPLIT, class TY>
+static bool split_xty(const double* X, int64_t ldx, int mx, const double* rowscale, const TY* Y, int64_t ldy, int ny,
+                      int rows, double* C, int64_t ldc, bool accumulate, int lower_only, void* tp, double* part,
+                      const double* sc, int slots, const int* ab, hipStream_t s) {
+  typedef typename SplitT<SPLIT>::P P;
+  constexpr int NP = SplitT<SPLIT>::NP;
+  const int ldk = ldk_of(rows);
+  P* ta = (P*)tp;
+  P* tb = ta + (int64_t)NP * mx * ldk;
+  if (!split_t<SPLIT>(X, ldx, mx, rows, rowscale, ta, ldk, sc, s)) return false;
+  if (!split_t<SPLIT>(Y, ldy, ny, rows, nullptr, tb, ldk, sc ? sc + 1 : nullptr, s)) return false;
+  PlaneOp<P> a{ta, ldk, (int64_t)mx * ldk, nullptr}, b{tb, ldk, (int64_t)ny * ldk, nullptr};
+  const int64_t tiles = split_tiles((int)ceil_div(mx, 128), (int)ceil_div(ny, 64), 2, lower_only && mx == ny);
+  const int sp = part ? split_k_for(tiles, ldk, slots) : 1;
+  const int64_t cn = (int64_t)mx * ldc;
+  if (sp == 1) {
+    EpiStore<double> epi{C, ldc, mx, ny, 1.0, accumulate ? 1.0 : 0.0, nullptr, 0, 0};
+    return launch_split<SPLIT, 128, 64, 2, 2, 1>(mx, ny, ldk, a, b, a, b, 0, sc, epi, ab, s, lower_only);
+  }
+  EpiStore<double> epi{part, ldc, mx, ny, 1.0, 0.0, nullptr, cn, 0};
+  if (!launch_split<SPLIT, 128, 64, 2, 2, 1>(mx, ny, ldk, a, b, a, b, 0, sc, epi, ab, s, lower_only, sp))
+    return false;
+  hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(cn)), dim3(256), 0, s, C, (const double*)part, cn, sp,
+                     accumulate ? 1 : 0, ab);
+  return launch_ok();
 }
 
 // dX rows = Abar F (Abar: rows x 2 N_mu real form, F: packed Phi_mu) in the
@@ -413,21 +539,34 @@ static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec
   }
 }
 
-// One orbital set's share of the block: dX rows = Abar F, Q += Abar^T X.
+// One orbital set's share of the block: dX rows = Abar F, Q += Abar^T X
+// (split precisions: both on 16-bit matrix cores, Abar^T X through
+// transposed planes; else Abar^T X in the compute type, split over K).
 template <int PREC, class TS>
 static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const void* fplanes,
                           const TS* X, int64_t ld_x, int n, TS* dX, int64_t ld_dx, int64_t r, int rows, double* Q,
-                          double* Qpart, const double* scales, const AdjPlanes& ap, int sp, bool first,
-                          const int* ab, hipStream_t s) {
+                          double* Qpart, const double* scales, const AdjPlanes& ap, int sp, bool first, void* tp,
+                          double* tpart, int slots, const int* ab, hipStream_t s) {
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s))
     return false;
-  const int64_t qn = two_mu * 2 * n;
-  if (!tgemm<typename Prec<PREC>::Q, XC, XC>((int)two_mu, 2 * n, rows, Abar, two_mu, X + 2 * r * ld_x, 2 * ld_x,
-                                             Qpart, 2 * (int64_t)n, 1.0, 0.0, ab, s, sp, qn))
-    return false;
-  hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(qn)), dim3(256), 0, s, Q, Qpart, qn, sp, first ? 0 : 1, ab);
-  return launch_ok();
+  constexpr int SPLIT = Prec<PREC>::SPLIT;
+  if constexpr (SPLIT >= 0) {
+    // binary16 scales (s_Abar, s_X) = scales[0..1]
+    return split_xty<SPLIT, TS>(Abar, two_mu, (int)two_mu, nullptr, X + 2 * r * ld_x, 2 * ld_x, 2 * n, rows, Q,
+                                2 * (int64_t)n, !first, 0, tp, tpart, SPLIT == SPLIT_FP16X3 ? scales : nullptr, slots,
+                                ab, s);
+  } else {
+    (void)tp;
+    (void)tpart;
+    (void)slots;
+    const int64_t qn = two_mu * 2 * n;
+    if (!tgemm<typename Prec<PREC>::Q, XC, XC>((int)two_mu, 2 * n, rows, Abar, two_mu, X + 2 * r * ld_x, 2 * ld_x,
+                                               Qpart, 2 * (int64_t)n, 1.0, 0.0, ab, s, sp, qn))
+      return false;
+    hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(qn)), dim3(256), 0, s, Q, Qpart, qn, sp, first ? 0 : 1, ab);
+    return launch_ok();
+  }
 }
 
 // Mbar terms of one orbital set at the interpolation rows (small: N_mu rows).
@@ -518,16 +657,37 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       return ISDF_E_HIP;
     const BwdSplits sp_phi = bwd_splits(rows, n1, n_mu, n_phi, !tbar, P.slots);
     const BwdSplits sp_psi = bwd_splits(rows, n1, n_mu, n_psi, !tbar, P.slots);
+    constexpr int SPLIT = Prec<PREC>::SPLIT;
     if (!tbar) {
-      // H += G^T diag(g) G (lower tiles, split-K, fixed-order reduction)
-      const int sp = sp_phi.h;
-      const int64_t pn = (int64_t)n1 * n1;
-      if (!tgemm<double, XC, XC>(n1, n1, rows, Gb, n1, Gb, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
-        return ISDF_E_HIP;
-      hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp, first ? 0 : 1,
-                         ab);
-      // S = 2 g . (G (C C^H)^-2): Abar / Bbar in place and the loss, in the epilogue
-      EpiSAdj epi{Gb, n1, Ab, Bb, 2 * (int64_t)n_mu, g + r, rows, n1, aliased ? 1 : 0, P.lpart};
+      // H += G^T diag(g) G (lower tiles, fixed-order reduction): FP64 split-K,
+      // or, with split orbital contractions, on 16-bit matrix cores like them
+      // (a sum of non-negative terms; nothing here involves (C C^H)^-1)
+      if constexpr (SPLIT >= 0) {
+        const double* hsc = nullptr;
+        if (SPLIT == SPLIT_FP16X3) {  // binary16 scales of g G and G
+          if (!fill<double>(P.amax + 4, 2, 0.0, s)) return ISDF_E_HIP;
+          hipLaunchKernelGGL(absmax_real2, dim3((unsigned)(rows < 2048 ? rows : 2048)), dim3(256), 0, s,
+                             (const double*)Gb, (int64_t)n1, n1, (int64_t)rows, g + r, P.amax + 4);
+          hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 12, 4, 5, 4, 5);
+          if (!launch_ok()) return ISDF_E_HIP;
+          hsc = P.sc + 12;
+        }
+        if (!split_xty<SPLIT, double>(Gb, n1, n1, g + r, Gb, n1, n1, rows, P.P, n1, !first, 1, P.tp, P.tpart, hsc,
+                                      P.slots, ab, s))
+          return ISDF_E_HIP;
+      } else {
+        const int sp = sp_phi.h;
+        const int64_t pn = (int64_t)n1 * n1;
+        if (!tgemm<double, XC, XC>(n1, n1, rows, Gb, n1, Gb, n1, P.Ppart, n1, 1.0, 0.0, ab, s, sp, pn, g + r, 1))
+          return ISDF_E_HIP;
+        hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(pn)), dim3(256), 0, s, P.P, P.Ppart, pn, sp,
+                           first ? 0 : 1, ab);
+      }
+      // S = 2 g . (G (C C^H)^-2): Abar / Bbar in place, the loss and (binary16
+      // split) the largest |Abar|, |Bbar| for their scales, in the epilogue
+      if (SPLIT == SPLIT_FP16X3 && !fill<double>(P.amax + 2, 2, 0.0, s)) return ISDF_E_HIP;
+      EpiSAdj epi{Gb,  n1, Ab, Bb, 2 * (int64_t)n_mu, g + r, rows, n1, aliased ? 1 : 0, P.lpart,
+                  SPLIT == SPLIT_FP16X3 ? P.amax + 2 : nullptr};
       Operand<double> a{Gb, n1, nullptr, nullptr}, b{P.W2, n1, nullptr, nullptr};
       if (!launch_gemm<double, 128, 128, 16, 2, 2, double, KC, double, KC, 1>(rows, n1, n1, a, b, a, b, 0, epi, 0, ab,
                                                                              s))
@@ -552,18 +712,21 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                          Ab, Bb, (int64_t)rows, n_mu, aliased ? 1 : 0);
       if (!launch_ok()) return ISDF_E_HIP;
     }
-    if (Prec<PREC>::SPLIT == SPLIT_FP16X3) {  // binary16 scales of Abar, Phi, Bbar, Psi
-      if (!fill<double>(P.amax + 2, 2, 0.0, s)) return ISDF_E_HIP;
-      if (!absmax<double>(Abar, n_mu, n_mu, rows, P.amax + 2, s)) return ISDF_E_HIP;
-      if (!aliased && !absmax<double>(Bbar, n_mu, n_mu, rows, P.amax + 3, s)) return ISDF_E_HIP;
+    if (SPLIT == SPLIT_FP16X3) {  // binary16 scales of Abar, Phi, Bbar, Psi
+      if (tbar) {  // (the fused loss found the maxima in its epilogue)
+        if (!fill<double>(P.amax + 2, 2, 0.0, s)) return ISDF_E_HIP;
+        if (!absmax<double>(Abar, n_mu, n_mu, rows, P.amax + 2, s)) return ISDF_E_HIP;
+        if (!aliased && !absmax<double>(Bbar, n_mu, n_mu, rows, P.amax + 3, s)) return ISDF_E_HIP;
+      }
       hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 4, 2, 0, 3,
                          aliased ? 0 : 1);
     }
     if (!orbital_block<PREC, TS>(Abar, n_mu, Fphi, P.ap.f_phi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi,
-                                 P.Qpart, P.sc + 4, P.ap, sp_phi.q, first, ab, s))
+                                 P.Qpart, P.sc + 4, P.ap, sp_phi.q, first, P.tp, P.tpart, P.slots, ab, s))
       return ISDF_E_HIP;
     if (!aliased && !orbital_block<PREC, TS>(Bbar, n_mu, Fpsi, P.ap.f_psi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows,
-                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, sp_psi.q, first, ab, s))
+                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, sp_psi.q, first, P.tp, P.tpart, P.slots,
+                                             ab, s))
       return ISDF_E_HIP;
   }
   if (!(phases & BWD_END)) return ISDF_OK;

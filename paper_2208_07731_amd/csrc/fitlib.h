@@ -375,20 +375,24 @@ struct Prec<ISDF_P_FP16X3> {
 // Slices between FP64 folds of the leading accumulator.
 constexpr int SPLIT_FLUSH = 2;
 
+// lower_only (M = N): only the tiles that reach the lower triangle, for
+// symmetric products whose upper triangle is mirrored afterwards.
 template <int MODE, int BM, int BN, int WM, int WN, int NOPS, class Epi>
 static bool launch_split(int M, int N, int64_t K, PlaneOp<typename SplitT<MODE>::P> A0,
                          PlaneOp<typename SplitT<MODE>::P> B0, PlaneOp<typename SplitT<MODE>::P> A1,
                          PlaneOp<typename SplitT<MODE>::P> B1, int64_t K1, const double* scales, const Epi& epi,
-                         const int* abort, hipStream_t st) {
+                         const int* abort, hipStream_t st, int lower_only = 0, int splits = 1) {
+  static_assert(BM % BN == 0, "tile");
   if (M <= 0 || N <= 0) return true;
   GemmShape sh{};
   sh.M = M;
   sh.N = N;
   sh.K = K;
-  sh.kchunk = K;
-  sh.splits = 1;
+  sh.splits = NOPS == 1 && splits > 1 ? splits : 1;
+  sh.kchunk = sh.splits > 1 ? ceil_div(ceil_div(K, sh.splits), 32) * 32 : K;  // whole 32-deep slices
+  sh.lower_only = lower_only && M == N;
   sh.abort = abort;
-  const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
+  const int64_t tiles = split_tiles((int)ceil_div(M, BM), (int)ceil_div(N, BN), BM / BN, sh.lower_only) * sh.splits;
   hipLaunchKernelGGL((gemm_split_kernel<MODE, BM, BN, WM, WN, NOPS, SPLIT_FLUSH, Epi>), dim3((unsigned)tiles),
                      dim3(WM * WN * ISDF_WAVE), 0, st, sh, A0, B0, A1, B1, K1, scales, epi);
   return launch_ok();

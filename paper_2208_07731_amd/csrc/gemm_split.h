@@ -157,8 +157,9 @@ __device__ __forceinline__ void flush_acc(f4v (&acc)[Cfg::MI][Cfg::NI], d4v (&ac
 template <int MODE, class Cfg, int BM, int BN, int FLUSH>
 __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::P>& A,
                                            const PlaneOp<typename SplitT<MODE>::P>& B, int m0, int n0, int M, int N,
-                                           int64_t K, typename SplitT<MODE>::P* smem, f4v (&acc0)[Cfg::MI][Cfg::NI],
-                                           f4v (&acc1)[Cfg::MI][Cfg::NI], d4v (&accd)[Cfg::MI][Cfg::NI]) {
+                                           int64_t kbeg, int64_t K, typename SplitT<MODE>::P* smem,
+                                           f4v (&acc0)[Cfg::MI][Cfg::NI], f4v (&acc1)[Cfg::MI][Cfg::NI],
+                                           d4v (&accd)[Cfg::MI][Cfg::NI]) {
   typedef SplitT<MODE> S;
   typedef typename S::P P;
   typedef typename S::V V;
@@ -171,15 +172,15 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
   PlaneStager<MODE, BN, Cfg::THREADS> sb;
   sa.init(A, m0, M, tid);
   sb.init(B, n0, N, tid);
-  if (K <= 0) return;
-  sa.load(A, 0, tid);
-  sb.load(B, 0, tid);
+  if (K <= kbeg) return;
+  sa.load(A, kbeg, tid);
+  sb.load(B, kbeg, tid);
   sa.store(As, LDK, tid);
   sb.store(Bs, LDK, tid);
   __syncthreads();
   const int q8 = 8 * (lane >> 4);
   int step = 0;
-  for (int64_t k0 = 0; k0 < K; k0 += Cfg::BK) {
+  for (int64_t k0 = kbeg; k0 < K; k0 += Cfg::BK) {
     const bool more = k0 + Cfg::BK < K;
     if (more) {
       sa.load(A, k0 + Cfg::BK, tid);
@@ -252,6 +253,51 @@ __global__ void split_planes(const TS* __restrict__ x, int64_t ld, int n, const 
   }
 }
 
+// Transposed split: planes [NP][ncols][ldk] of the 16-bit parts of the
+// columns of an r-major block, x(c, k) = X[k ld + c] (times rowscale[k] when
+// given), k < rows, and zero for rows <= k < ldk: the grid rows become the
+// contiguous K index of a product contracted over them (X^T Y).  One tile
+// of 64 rows x 64 columns per workgroup, transposed through LDS; scale as in
+// split_planes.
+template <int MODE, class TS>
+__global__ __launch_bounds__(256) void split_planes_t(const TS* __restrict__ X, int64_t ld, int ncols, int rows,
+                                                      const double* __restrict__ rowscale,
+                                                      typename SplitT<MODE>::P* __restrict__ out, int ldk,
+                                                      int64_t pstride, const double* scale) {
+  typedef SplitT<MODE> S;
+  __shared__ double tile[64][65];
+  const double sc = scale ? *scale : 1.0;
+  const int k0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int kk = ty; kk < 64; kk += 4) {
+    const int k = k0 + kk, c = c0 + tx;
+    double v = 0.0;
+    if (k < rows && c < ncols) {
+      v = (double)X[(int64_t)k * ld + c];
+      if (rowscale) v *= rowscale[k];
+    }
+    tile[kk][tx] = v;
+  }
+  __syncthreads();
+  // 64 columns x 8 runs of 8 consecutive k, two per thread
+  for (int q = threadIdx.x; q < 512; q += 256) {
+    const int cc = q >> 3, run = q & 7;
+    const int c = c0 + cc, kb = k0 + 8 * run;
+    if (c >= ncols || kb >= ldk) continue;
+    typename S::V w[S::NP];
+#pragma unroll
+    for (int e8 = 0; e8 < 8; ++e8) {
+      typename S::P o[S::NP];
+      S::split(tile[8 * run + e8][cc], sc, o);
+#pragma unroll
+      for (int p = 0; p < S::NP; ++p) w[p][e8] = o[p];
+    }
+#pragma unroll
+    for (int p = 0; p < S::NP; ++p)
+      *reinterpret_cast<typename S::V*>(out + p * pstride + (int64_t)c * ldk + kb) = w[p];
+  }
+}
+
 // Power-of-two operand scales for the FP16 split, from device magnitudes:
 // scales[2 i] = 2^e with max |x| 2^e <= 2^14 (1 if the operand is zero).
 __device__ __forceinline__ double pow2_scale_for(double amax) {
@@ -261,8 +307,19 @@ __device__ __forceinline__ double pow2_scale_for(double amax) {
   return ldexp(1.0, 14 - e);
 }
 
+// Tiles of a split-engine launch: all of them, or (lower_only, M = N, BM a
+// multiple q of BN) those that reach the lower triangle: q (tm + 1) in row
+// block tm, capped at tiles_n in the last one.
+__host__ __device__ __forceinline__ int64_t split_tiles(int tiles_m, int tiles_n, int q, int lower_only) {
+  if (!lower_only) return (int64_t)tiles_m * tiles_n;
+  const int64_t last = (int64_t)q * tiles_m < tiles_n ? (int64_t)q * tiles_m : tiles_n;
+  return (int64_t)q * (tiles_m - 1) * tiles_m / 2 + last;
+}
+
 // NOPS = 1 or 2 operand pairs (two pairs: two accumulator sets, e.g. the
-// Gram blocks of Phi and Psi for the same tile).  scales: null (BF16X6) or
+// Gram blocks of Phi and Psi for the same tile).  With sh.splits > 1 (one
+// operand pair only) the grid holds sh.splits groups of tiles, group z
+// summing K slice [z kchunk, (z + 1) kchunk) and handing z to the epilogue.  scales: null (BF16X6) or
 // device [s_A0, s_B0, s_A1, s_B1] the planes were scaled by (FP16X3).
 template <int MODE, int BM, int BN, int WM, int WN, int NOPS, int FLUSH, class Epi>
 __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
@@ -274,13 +331,29 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
   if (sh.abort && *sh.abort) return;
   __shared__ __attribute__((aligned(16))) typename S::P smem[S::NP * (BM + BN) * Cfg::LDK];
   const int tiles_n = (sh.N + BN - 1) / BN, tiles_m = (sh.M + BM - 1) / BM;
-  const int ntiles = tiles_m * tiles_n;
-  const int logical = xcd_remap(blockIdx.x, ntiles);
-  const int tm = logical / tiles_n, tn = logical % tiles_n;
+  const int ntiles = (int)split_tiles(tiles_m, tiles_n, BM / BN, sh.lower_only);
+  // split-K: slice z of the K range per group of ntiles workgroups
+  const int z = blockIdx.x / ntiles;
+  const int logical = xcd_remap(blockIdx.x % ntiles, ntiles);
+  const int64_t kbeg = (int64_t)z * sh.kchunk;
+  const int64_t kend = kbeg + sh.kchunk < sh.K ? kbeg + sh.kchunk : sh.K;
+  int tm, tn;
+  if (sh.lower_only) {
+    // row block tm holds the q (tm + 1) column tiles that reach its last row
+    // (q = BM / BN): logical = q tm (tm + 1) / 2 + tn
+    constexpr int q = BM / BN;
+    tm = (int)((sqrt(1.0 + 8.0 * logical / q) - 1.0) * 0.5);
+    while (tm > 0 && (int64_t)q * tm * (tm + 1) / 2 > logical) --tm;
+    while (tm + 1 < tiles_m && (int64_t)q * (tm + 1) * (tm + 2) / 2 <= logical) ++tm;
+    tn = logical - q * tm * (tm + 1) / 2;
+  } else {
+    tm = logical / tiles_n;
+    tn = logical % tiles_n;
+  }
   const int m0 = tm * BM, n0 = tn * BN;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv / (BN / Cfg::WTN), wn = wv % (BN / Cfg::WTN);
-  TileAt at{m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, 0, 0};
+  TileAt at{m0 + wm * Cfg::WTM, n0 + wn * Cfg::WTN, lane, z, 0};
   double u0 = 1.0, u1 = 1.0;
   if (scales) {
     u0 = 1.0 / (scales[0] * scales[1]);
@@ -295,7 +368,7 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
       c0[i][j] = c1[i][j] = f4v{0, 0, 0, 0};
       r0[i][j] = d4v{0, 0, 0, 0};
     }
-  split_loop<MODE, Cfg, BM, BN, FLUSH>(A0, B0, m0, n0, sh.M, sh.N, sh.K, smem, c0, c1, r0);
+  split_loop<MODE, Cfg, BM, BN, FLUSH>(A0, B0, m0, n0, sh.M, sh.N, kbeg, kend, smem, c0, c1, r0);
 #pragma unroll
   for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
@@ -312,7 +385,7 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
         r1[i][j] = d4v{0, 0, 0, 0};
       }
     __syncthreads();
-    split_loop<MODE, Cfg, BM, BN, FLUSH>(A1, B1, m0, n0, sh.M, sh.N, K1, smem, c0, c1, r1);
+    split_loop<MODE, Cfg, BM, BN, FLUSH>(A1, B1, m0, n0, sh.M, sh.N, 0, K1, smem, c0, c1, r1);
 #pragma unroll
     for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
