@@ -74,7 +74,7 @@ MFMA_PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x6": 2500.0, "fp16x3": 2500.0}  #
 ISSUED = {"fp64": 1, "fp32": 1, "bf16x6": 6, "fp16x3": 3}  # MFMA products per algorithmic product
 
 
-def phase_rates(wl, prec: str, phases: dict, rounds: int, saved_gram: bool = False) -> dict:
+def phase_rates(wl, prec: str, phases: dict, rounds: int, saved_gram: bool = False, km: dict | None = None) -> dict:
     """Algorithmic work of each phase, its rate and its fraction of the
     roofline that bounds it.
 
@@ -101,6 +101,9 @@ def phase_rates(wl, prec: str, phases: dict, rounds: int, saved_gram: bool = Fal
     out["kmeans"] = {"ms": ms, "bound": "hbm", "bytes": km_bytes, "GB/s": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK, 4), "rounds": rounds,
                      "brute_force_pairs": (rounds + 1) * wl.n_r * wl.n_mu}
+    if km is not None:  # what the pruned classification actually evaluated
+        out["kmeans"]["evaluated_pairs"] = km.get("pairs_evaluated")
+        out["kmeans"]["bound_tests"] = km.get("bound_tests")
     work = {
         "factor": (8.0 * wl.n_mu ** 2 * n_e + float(n1) ** 3, "fp64", 1),
         "zc": (8.0 * wl.n_r * wl.n_mu * n_e, prec, ISSUED[prec]),
@@ -543,7 +546,7 @@ def main():
                                + (" (Gram blocks kept for the adjoint)" if st.save_gram else ""),
                    "gram_prec": args.prec},
         "phases_ms": phases,
-        "phases": phase_rates(wl, args.prec, phases, info["kmeans"]["iters"], st.save_gram),
+        "phases": phase_rates(wl, args.prec, phases, info["kmeans"]["iters"], st.save_gram, info["kmeans"]),
         "kmeans": {"rounds": info["kmeans"]["iters"], "converged": info["kmeans"]["converged"]},
         "roofline": {"bound": "mfma", "kernel": "FP64 GEMM Theta = (Z C^H)(C C^H)^-1 (one r-block per launch)",
                      "achieved": round(achieved, 2), "peak": PEAK["fp64"], "unit": "TFLOP/s",

@@ -99,6 +99,9 @@ typedef struct {
   int32_t near_ties;    /* points with (d2 - d1) <= near_tie_rel * d2 */
   int32_t changed;      /* labels changed by the last round that ran */
   double objective;     /* sum_p w_p |r_p - c_label(p)|^2 at the final classification */
+  int64_t pairs_evaluated; /* point-centroid distances evaluated, all classifications
+                              (a full scan would take N_r n_mu per classification) */
+  int64_t bound_tests;  /* brick-centroid lower-bound tests that chose them */
 } isdf_kmeans_info;
 
 /* Bytes of workspace isdf_kmeans needs.  Host-only, never synchronises. */
@@ -151,9 +154,8 @@ int isdf_kmeans(const isdf_grid* grid /* host */, int32_t dt,
  *   centroids, labels, w   required here (isdf_kmeans may carve them from the
  *                          workspace when they are NULL)
  *   stream                 must belong to the current device (else ISDF_E_ARG)
- * Requests whose scratch (about 24 n_mu + 24 max_iter + N_r / 64 bytes plus
- * 2 KiB of alignment) exceeds 4 MiB return ISDF_E_SCRATCH before anything
- * is enqueued.  Every call on a GPU shares that GPU's scratch, and each
+ * Requests whose scratch (about 56 n_mu + 40 max_iter + N_r / 64 bytes plus
+ * 36 KiB) exceeds 4 MiB return ISDF_E_SCRATCH before anything is enqueued.  Every call on a GPU shares that GPU's scratch, and each
  * call re-initialises what it reads: calls that overlap on one GPU (on
  * different streams, or from different host threads without ordering) race
  * and give undefined results; calls ordered on one stream do not.

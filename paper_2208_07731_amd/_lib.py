@@ -30,7 +30,8 @@ class Grid(C.Structure):
 class KmeansInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("converged", C.c_int32),
                 ("empty_update", C.c_int32), ("empty_final", C.c_int32), ("ties", C.c_int32),
-                ("near_ties", C.c_int32), ("changed", C.c_int32), ("objective", C.c_double)]
+                ("near_ties", C.c_int32), ("changed", C.c_int32), ("objective", C.c_double),
+                ("pairs_evaluated", C.c_int64), ("bound_tests", C.c_int64)]
 
 
 class QrcpInfo(C.Structure):

@@ -4,12 +4,15 @@
 // Kernels, in launch order:
 //   km_weight  one HBM pass over the orbital rows -> w[N_r] (FP64)
 //   km_init    seeds, counters and per-cluster bounding boxes
-//   km_assign  classification: argmin over centroids staged in LDS, one
-//              4x4x4 brick of grid points per wavefront; also the objective
-//              partials, tie counts, changed-label count and per-cluster
+//   km_assign  classification, one 4x4x4 brick of grid points per wavefront:
+//              first round, argmin over every centroid staged through LDS;
+//              later rounds, over the centroids of the cells near the brick
+//              (km_bin); also the objective partials, tie counts,
+//              changed-label count, evaluated-pair counts and per-cluster
 //              bounding boxes (integer atomics, order independent)
 //   km_update  weighted centroids: one wavefront per cluster scans its
 //              bounding box in a fixed order -> deterministic FP64 sums
+//   km_bin     the updated centroids sorted into a coarse grid of cells
 //   km_snap    member nearest to each final centroid (lowest index on ties)
 //   km_final   info struct
 // A round that changes no label sets a device flag that turns the remaining
@@ -46,6 +49,10 @@ struct KmArrays {
   double* w;       // [N_r]
   int* bbox;       // [K][6]: imin, imax, jmin, jmax, kmin, kmax
   double* jpart;   // [assign blocks]
+  int* cell_start;  // [cells + 1]: centroids of cell q at cell_c[cell_start[q] .. cell_start[q + 1])
+  double4* cell_c;  // [K]: (x, y, z, index) of the centroids, by cell
+  unsigned long long* pairs;  // [assign blocks] point-centroid distances evaluated, over all classifications
+  unsigned long long* tests;  // [assign blocks] brick-centroid bound tests, over all classifications
 };
 
 struct KmGeom {
@@ -53,10 +60,14 @@ struct KmGeom {
   int nb0, nb1, nb2;  // bricks per axis (4 points each)
   double s0, s1, s2;  // metric weights (h_a / min h)^2
   int aniso;
+  int cell;           // edge of a centroid cell in grid points
+  int nc0, nc1, nc2;  // cells per axis
 };
 
 constexpr int ASSIGN_THREADS = 512;  // 8 wavefronts = 8 bricks
 constexpr int CTILE = 2048;          // centroids staged per LDS tile
+constexpr int MAX_CELLS = 8192;      // centroid cells (counted in LDS by km_bin)
+constexpr int BIN_THREADS = 1024;
 
 // Squared distance with the same operation order as the definition
 // ((s0 dx^2 + s1 dy^2) + s2 dz^2); contraction off so that the value is the
@@ -135,7 +146,7 @@ __global__ void km_check_weight(const double* __restrict__ w, int64_t nr, KmStat
 }
 
 // ------------------------------------------------------------------ init
-__global__ void km_init(KmArrays a, const double* __restrict__ c0, int K, int T, int64_t nr) {
+__global__ void km_init(KmArrays a, const double* __restrict__ c0, int K, int T, int64_t nr, int nparts) {
   int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (tid == 0) {
@@ -152,6 +163,10 @@ __global__ void km_init(KmArrays a, const double* __restrict__ c0, int K, int T,
     a.nearc[i] = 0;
     a.empty[i] = 0;
     a.jhist[i] = -1.0;
+  }
+  for (int64_t i = tid; i < nparts; i += stride) {
+    a.pairs[i] = 0;
+    a.tests[i] = 0;
   }
   for (int64_t i = tid; i < 3 * (int64_t)K; i += stride) a.cent[i] = c0[i];
   for (int64_t i = tid; i < K; i += stride) {
@@ -177,6 +192,7 @@ __global__ void km_init(KmArrays a, const double* __restrict__ c0, int K, int T,
 // exact ties and near-tie counts are those of the full scan.  Survivors are
 // evaluated in increasing centroid order (lowest index wins ties).
 constexpr int SURV = 128;  // per-wavefront survivor list
+static_assert(SURV <= CTILE / (ASSIGN_THREADS / ISDF_WAVE), "survivor coordinates fit a wave's tile slice");
 
 __device__ __forceinline__ double axis_lb(double c, double lo, double hi) {
   const double d = fmax(fmax(lo - c, c - hi), 0.0);
@@ -193,6 +209,9 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
   __shared__ double cx[CTILE], cy[CTILE], cz[CTILE];
   __shared__ double jw[ASSIGN_THREADS / ISDF_WAVE];
   __shared__ int surv[ASSIGN_THREADS / ISDF_WAVE][SURV];
+  __shared__ int cellst[ASSIGN_THREADS / ISDF_WAVE][ISDF_WAVE], celloff[ASSIGN_THREADS / ISDF_WAVE][ISDF_WAVE];
+  __shared__ unsigned long long wpairs[ASSIGN_THREADS / ISDF_WAVE], wtests[ASSIGN_THREADS / ISDF_WAVE];
+  __shared__ int wcount[ASSIGN_THREADS / ISDF_WAVE][3];
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -217,12 +236,12 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
   double d1 = INFINITY, d2 = INFINITY;
   int lab = 0;
   const int64_t p = ((int64_t)pi * g.n1 + pj) * g.n2 + pk;
-  // pass 1: U, an upper bound of every brick point's nearest distance.  After
-  // the first round: the largest distance of a point to its current cluster's
-  // centroid (labels from the previous round, centroids just updated);
-  // first round: the smallest over centroids of the farthest brick distance.
-  double U = INFINITY;
+  unsigned long long n_eval = 0, n_test = 0;  // survivors evaluated, bound tests (wave-uniform)
   if (t > 0) {
+    // U: the largest distance of a brick point to the centroid of the
+    // cluster it was given in the previous round, with the centroids as
+    // they are now (just updated): a distance to a current centroid, so it
+    // bounds every brick point's nearest distance
     double own = -INFINITY;
     if (valid) {
       const int old = a.labels[p];
@@ -231,33 +250,115 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) own = fmax(own, __shfl_xor(own, o, ISDF_WAVE));
-    U = own;
-  }
-  for (int c0 = 0; c0 < K && t == 0; c0 += CTILE) {
-    const int cn = min(CTILE, K - c0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < cn; i += ASSIGN_THREADS) {
-      cx[i] = a.cent[3 * (int64_t)(c0 + i) + 0];
-      cy[i] = a.cent[3 * (int64_t)(c0 + i) + 1];
-      cz[i] = a.cent[3 * (int64_t)(c0 + i) + 2];
-    }
-    __syncthreads();
-    for (int m = lane; m < cn; m += ISDF_WAVE) {
-      const double ub = (g.s0 * axis_ub(cx[m], lo0, hi0) + g.s1 * axis_ub(cy[m], lo1, hi1)) +
-                        g.s2 * axis_ub(cz[m], lo2, hi2);
-      U = fmin(U, ub);
-    }
-  }
-  if (t == 0) {
+    const double cut = own * margin;
+    // a centroid with lb <= cut lies within sqrt(cut / s_a) of the brick on
+    // every axis a, so only the cells of that box can hold one
+    int c_lo[3], c_hi[3];
+    const double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2}, sa[3] = {g.s0, g.s1, g.s2};
+    const int nca[3] = {g.nc0, g.nc1, g.nc2};
+    int nbox = 1;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) U = fmin(U, __shfl_xor(U, o, ISDF_WAVE));
-  }
-  const double cut = U * margin;
-  // pass 2: survivors of each tile, in increasing index, then the exact scan
-  const bool one_tile = K <= CTILE && t == 0;  // the tile is still in LDS from pass 1
-  for (int c0 = 0; c0 < K; c0 += CTILE) {
-    const int cn = min(CTILE, K - c0);
-    if (!one_tile) {
+    for (int ax = 0; ax < 3; ++ax) {
+      const double r = cut > 0.0 ? sqrt(cut / sa[ax]) * (1.0 + 1e-12) + 1e-9 : 0.0;
+      c_lo[ax] = max(0, (int)floor((lo[ax] - r) / g.cell));
+      c_hi[ax] = min(nca[ax] - 1, (int)floor((hi[ax] + r) / g.cell));
+      if (!(cut >= 0.0) || c_hi[ax] < c_lo[ax]) nbox = 0;  // no valid point in the brick
+      else nbox *= c_hi[ax] - c_lo[ax] + 1;
+    }
+    const int e1 = c_hi[1] - c_lo[1] + 1, e2 = c_hi[2] - c_lo[2] + 1;
+    int* cst = cellst[wv];
+    int* cof = celloff[wv];
+    // survivors' coordinates: this wave's slice of the first round's tile arrays
+    double* sx = cx + wv * (CTILE / (ASSIGN_THREADS / ISDF_WAVE));
+    double* sy = cy + wv * (CTILE / (ASSIGN_THREADS / ISDF_WAVE));
+    double* sz = cz + wv * (CTILE / (ASSIGN_THREADS / ISDF_WAVE));
+    int nlist = 0;
+    for (int b0 = 0; b0 < nbox; b0 += ISDF_WAVE) {
+      // one cell of the box per lane: its first entry and its count
+      const int q = b0 + lane;
+      int cs = 0, cn = 0;
+      if (q < nbox) {
+        const int qk = q % e2, qj = (q / e2) % e1, qi = q / (e1 * e2);
+        const int cell = ((c_lo[0] + qi) * g.nc1 + (c_lo[1] + qj)) * g.nc2 + (c_lo[2] + qk);
+        cs = a.cell_start[cell];
+        cn = a.cell_start[cell + 1] - cs;
+      }
+      int incl = cn;  // inclusive prefix sum over the lanes
+#pragma unroll
+      for (int o = 1; o < ISDF_WAVE; o <<= 1) {
+        const int v = __shfl_up(incl, o, ISDF_WAVE);
+        if (lane >= o) incl += v;
+      }
+      const int total = __shfl(incl, ISDF_WAVE - 1, ISDF_WAVE);
+      const int ncell = min(ISDF_WAVE, nbox - b0);
+      cst[lane] = cs;
+      cof[lane] = incl - cn;
+      __builtin_amdgcn_wave_barrier();
+      for (int c0 = 0; c0 < total; c0 += ISDF_WAVE) {
+        const int qq = c0 + lane;
+        bool keep = false;
+        double4 cand = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (qq < total) {
+          int lo_i = 0, hi_i = ncell - 1;  // last cell lane whose offset <= qq
+          while (lo_i < hi_i) {
+            const int mid = (lo_i + hi_i + 1) >> 1;
+            if (cof[mid] <= qq) lo_i = mid;
+            else hi_i = mid - 1;
+          }
+          cand = a.cell_c[cst[lo_i] + (qq - cof[lo_i])];
+          const double lb = (g.s0 * axis_lb(cand.x, lo0, hi0) + g.s1 * axis_lb(cand.y, lo1, hi1)) +
+                            g.s2 * axis_lb(cand.z, lo2, hi2);
+          keep = lb <= cut;
+        }
+        n_test += (unsigned long long)min(ISDF_WAVE, total - c0);
+        const unsigned long long bal = __ballot(keep);
+        const int cnt = __popcll(bal);
+        if (nlist + cnt > SURV) {  // evaluate the list (wave-uniform)
+          for (int e = 0; e < nlist; ++e) {
+            const int m = list[e];
+            const double d = sqd(px - sx[e], py - sy[e], pz - sz[e], g);
+            if (d < d1 || (d == d1 && m < lab)) {
+              d2 = d1;
+              d1 = d;
+              lab = m;
+            } else {
+              d2 = fmin(d2, d);
+            }
+          }
+          n_eval += (unsigned long long)nlist;
+          nlist = 0;
+          __builtin_amdgcn_wave_barrier();
+        }
+        if (keep) {  // survivor: its index and coordinates into this wave's list
+          const int at = nlist + __popcll(bal & ((1ull << lane) - 1ull));
+          list[at] = (int)cand.w;
+          sx[at] = cand.x;
+          sy[at] = cand.y;
+          sz[at] = cand.z;
+        }
+        nlist += cnt;
+        __builtin_amdgcn_wave_barrier();
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int e = 0; e < nlist; ++e) {
+      const int m = list[e];
+      const double d = sqd(px - sx[e], py - sy[e], pz - sz[e], g);
+      if (d < d1 || (d == d1 && m < lab)) {
+        d2 = d1;
+        d1 = d;
+        lab = m;
+      } else {
+        d2 = fmin(d2, d);
+      }
+    }
+    n_eval += (unsigned long long)nlist;
+  } else {
+    // first round: U = the smallest over centroids of the farthest brick
+    // distance, then every centroid tile's survivors in increasing index
+    double U = INFINITY;
+    for (int c0 = 0; c0 < K; c0 += CTILE) {
+      const int cn = min(CTILE, K - c0);
       __syncthreads();
       for (int i = threadIdx.x; i < cn; i += ASSIGN_THREADS) {
         cx[i] = a.cent[3 * (int64_t)(c0 + i) + 0];
@@ -265,39 +366,70 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
         cz[i] = a.cent[3 * (int64_t)(c0 + i) + 2];
       }
       __syncthreads();
-    }
-    int nlist = 0;
-    for (int mb = 0; mb < cn; mb += ISDF_WAVE) {
-      const int m = mb + lane;
-      bool keep = false;
-      if (m < cn) {
-        const double lb = (g.s0 * axis_lb(cx[m], lo0, hi0) + g.s1 * axis_lb(cy[m], lo1, hi1)) +
-                          g.s2 * axis_lb(cz[m], lo2, hi2);
-        keep = lb <= cut;
+      for (int m = lane; m < cn; m += ISDF_WAVE) {
+        const double ub = (g.s0 * axis_ub(cx[m], lo0, hi0) + g.s1 * axis_ub(cy[m], lo1, hi1)) +
+                          g.s2 * axis_ub(cz[m], lo2, hi2);
+        U = fmin(U, ub);
       }
-      const unsigned long long bal = __ballot(keep);
-      const int cnt = __popcll(bal);
-      if (nlist + cnt > SURV) {  // flush the list (wave-uniform)
-        for (int q = 0; q < nlist; ++q) {
-          const int mm = list[q];
-          const double d = sqd(px - cx[mm], py - cy[mm], pz - cz[mm], g);
-          d2 = fmin(d2, fmax(d, d1));
-          const bool better = d < d1;
-          d1 = better ? d : d1;
-          lab = better ? c0 + mm : lab;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) U = fmin(U, __shfl_xor(U, o, ISDF_WAVE));
+    const double cut = U * margin;
+    const bool one_tile = K <= CTILE;  // the tile is still in LDS
+    for (int c0 = 0; c0 < K; c0 += CTILE) {
+      const int cn = min(CTILE, K - c0);
+      if (!one_tile) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < cn; i += ASSIGN_THREADS) {
+          cx[i] = a.cent[3 * (int64_t)(c0 + i) + 0];
+          cy[i] = a.cent[3 * (int64_t)(c0 + i) + 1];
+          cz[i] = a.cent[3 * (int64_t)(c0 + i) + 2];
         }
-        nlist = 0;
+        __syncthreads();
       }
-      if (keep) list[nlist + __popcll(bal & ((1ull << lane) - 1ull))] = m;
-      nlist += cnt;
+      int nlist = 0;
+      n_test += (unsigned long long)cn;
+      for (int mb = 0; mb < cn; mb += ISDF_WAVE) {
+        const int m = mb + lane;
+        bool keep = false;
+        if (m < cn) {
+          const double lb = (g.s0 * axis_lb(cx[m], lo0, hi0) + g.s1 * axis_lb(cy[m], lo1, hi1)) +
+                            g.s2 * axis_lb(cz[m], lo2, hi2);
+          keep = lb <= cut;
+        }
+        const unsigned long long bal = __ballot(keep);
+        const int cnt = __popcll(bal);
+        if (nlist + cnt > SURV) {  // flush the list (wave-uniform)
+          for (int q = 0; q < nlist; ++q) {
+            const int mm = list[q];
+            const double d = sqd(px - cx[mm], py - cy[mm], pz - cz[mm], g);
+            d2 = fmin(d2, fmax(d, d1));
+            const bool better = d < d1;
+            d1 = better ? d : d1;
+            lab = better ? c0 + mm : lab;
+          }
+          n_eval += (unsigned long long)nlist;
+          nlist = 0;
+        }
+        if (keep) list[nlist + __popcll(bal & ((1ull << lane) - 1ull))] = m;
+        nlist += cnt;
+      }
+      for (int q = 0; q < nlist; ++q) {
+        const int mm = list[q];
+        const double d = sqd(px - cx[mm], py - cy[mm], pz - cz[mm], g);
+        d2 = fmin(d2, fmax(d, d1));
+        const bool better = d < d1;
+        d1 = better ? d : d1;
+        lab = better ? c0 + mm : lab;
+      }
+      n_eval += (unsigned long long)nlist;
     }
-    for (int q = 0; q < nlist; ++q) {
-      const int mm = list[q];
-      const double d = sqd(px - cx[mm], py - cy[mm], pz - cz[mm], g);
-      d2 = fmin(d2, fmax(d, d1));
-      const bool better = d < d1;
-      d1 = better ? d : d1;
-      lab = better ? c0 + mm : lab;
+  }
+  {  // this wave's counts, summed per workgroup below (no atomics on shared counters)
+    const int nvalid = __popcll(__ballot(valid));
+    if (lane == 0) {
+      wpairs[wv] = nvalid > 0 ? n_eval * (unsigned long long)nvalid : 0ull;
+      wtests[wv] = nvalid > 0 ? n_test : 0ull;
     }
   }
 
@@ -315,34 +447,63 @@ __global__ __launch_bounds__(ASSIGN_THREADS) void km_assign(KmArrays a, KmGeom g
   jv = wave_sum(jv);
   if (lane == 0) jw[wv] = jv;
   unsigned long long bc = __ballot(chg), bt = __ballot(tie), bn = __ballot(nr_tie);
-  if (lane == 0) {
-    if (bc) atomicAdd(&a.changed[t], __popcll(bc));
-    if (bt) atomicAdd(&a.ties[t], __popcll(bt));
-    if (bn) atomicAdd(&a.nearc[t], __popcll(bn));
+  if (lane == 0) {  // summed per workgroup below: one atomic per workgroup and counter
+    wcount[wv][0] = __popcll(bc);
+    wcount[wv][1] = __popcll(bt);
+    wcount[wv][2] = __popcll(bn);
   }
-  // per-cluster bounding boxes: one atomic set per distinct label in the brick
+  // per-cluster bounding boxes: one atomic set per distinct label in the
+  // brick.  Lane l holds brick point (l / 16, (l / 4) % 4, l % 4), so the
+  // extent of a label's points on each axis follows from its lane mask with
+  // scalar bit operations.
   unsigned long long act = __ballot(valid);
   while (act) {
-    int leader = __ffsll((long long)act) - 1;
-    int L = __shfl(lab, leader, ISDF_WAVE);
-    bool mine = valid && lab == L;
-    unsigned long long mm = __ballot(mine);
-    int imin = wave_min_i(mine ? pi : INT_MAX), imax = wave_max_i(mine ? pi : INT_MIN);
-    int jmin = wave_min_i(mine ? pj : INT_MAX), jmax = wave_max_i(mine ? pj : INT_MIN);
-    int kmin = wave_min_i(mine ? pk : INT_MAX), kmax = wave_max_i(mine ? pk : INT_MIN);
+    const int leader = __ffsll((long long)act) - 1;
+    const int L = __shfl(lab, leader, ISDF_WAVE);
+    const unsigned long long mm = __ballot(valid && lab == L);
     if (lane == leader) {
+      int i_lo = 4, i_hi = -1, j_lo = 4, j_hi = -1, k_lo = 4, k_hi = -1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if ((mm >> (16 * q)) & 0xFFFFull) {
+          i_lo = min(i_lo, q);
+          i_hi = max(i_hi, q);
+        }
+        if (mm & (0x000F000F000F000Full << (4 * q))) {
+          j_lo = min(j_lo, q);
+          j_hi = max(j_hi, q);
+        }
+        if (mm & (0x1111111111111111ull << q)) {
+          k_lo = min(k_lo, q);
+          k_hi = max(k_hi, q);
+        }
+      }
       int* b = a.bbox + 6 * (int64_t)L;
-      atomicMin(b + 0, imin); atomicMax(b + 1, imax);
-      atomicMin(b + 2, jmin); atomicMax(b + 3, jmax);
-      atomicMin(b + 4, kmin); atomicMax(b + 5, kmax);
+      atomicMin(b + 0, bi * 4 + i_lo); atomicMax(b + 1, bi * 4 + i_hi);
+      atomicMin(b + 2, bj * 4 + j_lo); atomicMax(b + 3, bj * 4 + j_hi);
+      atomicMin(b + 4, bk * 4 + k_lo); atomicMax(b + 5, bk * 4 + k_hi);
     }
     act &= ~mm;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int i = 0; i < ASSIGN_THREADS / ISDF_WAVE; ++i) s += jw[i];
+    unsigned long long np = 0, nt = 0;
+    int nc = 0, ntie = 0, nnear = 0;
+    for (int i = 0; i < ASSIGN_THREADS / ISDF_WAVE; ++i) {
+      s += jw[i];
+      np += wpairs[i];
+      nt += wtests[i];
+      nc += wcount[i][0];
+      ntie += wcount[i][1];
+      nnear += wcount[i][2];
+    }
+    if (nc) atomicAdd(&a.changed[t], nc);
+    if (ntie) atomicAdd(&a.ties[t], ntie);
+    if (nnear) atomicAdd(&a.nearc[t], nnear);
     a.jpart[blockIdx.x] = s;
+    a.pairs[blockIdx.x] += np;  // running totals over the classifications, one slot per workgroup
+    a.tests[blockIdx.x] += nt;
     if (blockIdx.x == 0) a.st->last_t = t;
   }
 }
@@ -459,6 +620,61 @@ __global__ __launch_bounds__(256) void km_update(KmArrays a, KmGeom g, int K, in
   if (blockIdx.x == 0 && threadIdx.x == 0) a.st->iters = t + 1;
 }
 
+// ------------------------------------------------------------------ bin
+// Sorts the centroids into cells of g.cell^3 grid points (one workgroup):
+// counts per cell, an exclusive scan into cell_start, then each centroid's
+// (x, y, z, index) at its cell's next free slot.  The order inside a cell
+// is unspecified; the classification does not depend on it (it keeps the
+// lowest index among equal distances explicitly).
+__device__ __forceinline__ int cell_of(double x, double y, double z, const KmGeom& g) {
+  const int i = min(g.nc0 - 1, max(0, (int)floor(x / g.cell)));
+  const int j = min(g.nc1 - 1, max(0, (int)floor(y / g.cell)));
+  const int k = min(g.nc2 - 1, max(0, (int)floor(z / g.cell)));
+  return (i * g.nc1 + j) * g.nc2 + k;
+}
+
+__global__ __launch_bounds__(BIN_THREADS) void km_bin(KmArrays a, KmGeom g, int K) {
+  if (a.st->done) return;
+  __shared__ int cnt[MAX_CELLS];
+  __shared__ int part[BIN_THREADS];
+  const int ncells = g.nc0 * g.nc1 * g.nc2;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ncells; i += BIN_THREADS) cnt[i] = 0;
+  __syncthreads();
+  for (int m = tid; m < K; m += BIN_THREADS) {
+    const double* c = a.cent + 3 * (int64_t)m;
+    atomicAdd(&cnt[cell_of(c[0], c[1], c[2], g)], 1);
+  }
+  __syncthreads();
+  // exclusive scan: each thread its run of `per` cells, then the run totals
+  const int per = (ncells + BIN_THREADS - 1) / BIN_THREADS;
+  const int b = tid * per, e = min(ncells, b + per);
+  int run = 0;
+  for (int i = b; i < e; ++i) run += cnt[i];
+  part[tid] = run;
+  __syncthreads();
+  for (int o = 1; o < BIN_THREADS; o <<= 1) {
+    const int v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int off = part[tid] - run;
+  for (int i = b; i < e; ++i) {
+    const int c = cnt[i];
+    cnt[i] = off;  // becomes the fill cursor
+    a.cell_start[i] = off;
+    off += c;
+  }
+  if (tid == 0) a.cell_start[ncells] = K;
+  __syncthreads();
+  for (int m = tid; m < K; m += BIN_THREADS) {
+    const double* c = a.cent + 3 * (int64_t)m;
+    const int pos = atomicAdd(&cnt[cell_of(c[0], c[1], c[2], g)], 1);
+    a.cell_c[pos] = make_double4(c[0], c[1], c[2], (double)m);
+  }
+}
+
 // ------------------------------------------------------------------ snap
 __global__ __launch_bounds__(256) void km_snap(KmArrays a, KmGeom g, int K, int32_t* __restrict__ idx) {
   const int lane = threadIdx.x & 63;
@@ -505,6 +721,16 @@ __global__ void km_final(KmArrays a, int nparts, isdf_kmeans_info* info, double*
   if (t >= 0 && lane == 0) a.jhist[t] = J;
   if (objective)
     for (int i = lane; i <= T; i += ISDF_WAVE) objective[i] = (i == t) ? J : a.jhist[i];
+  unsigned long long np = 0, nt = 0;  // integer sums: exact in any order
+  for (int i = lane; i < nparts; i += ISDF_WAVE) {
+    np += a.pairs[i];
+    nt += a.tests[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    np += __shfl_xor(np, o, ISDF_WAVE);
+    nt += __shfl_xor(nt, o, ISDF_WAVE);
+  }
   if (lane != 0) return;
   int status = ISDF_OK;
   if (st->nonfinite) status = ISDF_E_NONFINITE;
@@ -518,6 +744,8 @@ __global__ void km_final(KmArrays a, int nparts, isdf_kmeans_info* info, double*
   info->near_ties = t >= 0 ? a.nearc[t] : 0;
   info->changed = t >= 0 ? a.changed[t] : 0;
   info->objective = t >= 0 ? J : 0.0;
+  info->pairs_evaluated = (int64_t)np;
+  info->bound_tests = (int64_t)nt;
 }
 
 __global__ void copy_f64(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
@@ -543,6 +771,10 @@ static KmPlan plan_kmeans(void* ws, size_t cap, int64_t nr, int K, int T, int np
   P.a.jhist = c.take<double>(T + 1);
   P.a.bbox = c.take<int>(6 * (size_t)K);
   P.a.jpart = c.take<double>(nparts);
+  P.a.pairs = c.take<unsigned long long>(nparts);
+  P.a.tests = c.take<unsigned long long>(nparts);
+  P.a.cell_start = c.take<int>(MAX_CELLS + 1);
+  P.a.cell_c = c.take<double4>(K);
   if (own_cent) P.a.cent = c.take<double>(3 * (size_t)K);
   if (own_labels) P.a.labels = c.take<int>(nr);
   if (own_w) P.a.w = c.take<double>(nr);
@@ -565,6 +797,22 @@ static KmGeom make_geom(const isdf_grid* g) {
   G.s2 = (g->h[2] / hmin) * (g->h[2] / hmin);
   G.aniso = !(G.s0 == 1.0 && G.s1 == 1.0 && G.s2 == 1.0);
   return G;
+}
+
+// Centroid cells: about two centroids per cell (edge ~ (2 N_r / K)^(1/3)
+// grid points), at most MAX_CELLS of them.
+static void set_cells(KmGeom& G, int K) {
+  const double nr = (double)G.n0 * G.n1 * G.n2;
+  int e = (int)ceil(cbrt(2.0 * nr / K));
+  if (e < 1) e = 1;
+  for (;; ++e) {
+    const int64_t c = ceil_div(G.n0, e) * ceil_div(G.n1, e) * ceil_div(G.n2, e);
+    if (c <= MAX_CELLS) break;
+  }
+  G.cell = e;
+  G.nc0 = (int)ceil_div(G.n0, e);
+  G.nc1 = (int)ceil_div(G.n1, e);
+  G.nc2 = (int)ceil_div(G.n2, e);
 }
 
 static int assign_blocks(const KmGeom& G) {
@@ -654,13 +902,14 @@ static int kmeans_enqueue(const isdf_grid* grid, isdf_dtype dt, const void* phi,
     int64_t work = nr > 3 * (int64_t)n_mu ? nr : 3 * (int64_t)n_mu;
     int64_t blocks = ceil_div(work, 256);
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(km_init, dim3((unsigned)blocks), dim3(256), 0, st, P.a, c0, n_mu, max_iter, nr);
+    hipLaunchKernelGGL(km_init, dim3((unsigned)blocks), dim3(256), 0, st, P.a, c0, n_mu, max_iter, nr, nparts);
     if (!launch_ok()) return ISDF_E_HIP;
   }
   const int ublocks = (int)ceil_div(n_mu, 4);
   for (int t = 0; t < max_iter; ++t) {
     hipLaunchKernelGGL(km_assign, dim3(nparts), dim3(ASSIGN_THREADS), 0, st, P.a, G, n_mu, t, near_tie_rel);
     hipLaunchKernelGGL(km_update, dim3(ublocks), dim3(256), 0, st, P.a, G, n_mu, t, nparts);
+    hipLaunchKernelGGL(km_bin, dim3(1), dim3(BIN_THREADS), 0, st, P.a, G, n_mu);
   }
   hipLaunchKernelGGL(km_assign, dim3(nparts), dim3(ASSIGN_THREADS), 0, st, P.a, G, n_mu, max_iter,
                      near_tie_rel);
@@ -680,6 +929,7 @@ extern "C" int isdf_kmeans(const isdf_grid* grid, int32_t dt_in, const void* phi
                        near_tie_rel, idx, w, info));
   const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   KmGeom G = make_geom(grid);
+  set_cells(G, n_mu);
   const int nparts = assign_blocks(G);
   KmPlan P = plan_kmeans(ws, ws_bytes, nr, n_mu, max_iter, nparts, !centroids, !labels, !w, !objective);
   if (P.bytes > ws_bytes || !ws) return ISDF_E_WORKSPACE;
@@ -739,6 +989,7 @@ extern "C" int isdf_kmeans_noalloc(const isdf_grid* grid, int32_t dt_in, const v
   if (!centroids || !labels || !w) return ISDF_E_ARG;  // outputs the workspace form may carve
   const int64_t nr = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
   KmGeom G = make_geom(grid);
+  set_cells(G, n_mu);
   const int nparts = assign_blocks(G);
   if (plan_kmeans(nullptr, 0, nr, n_mu, max_iter, nparts, false, false, false, false).bytes > KM_SCRATCH_BYTES)
     return ISDF_E_SCRATCH;
