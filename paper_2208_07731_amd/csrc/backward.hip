@@ -377,8 +377,13 @@ struct BwdPlan {
   int* marker;   // [N_r] occupancy of the interpolation rows (check_idx)
   void *Ephi, *Epsi, *Fphi, *Fpsi, *Xphi, *Xpsi;
   double *G, *Th, *A, *B, *P, *Ppart, *Qphi, *Qpsi, *Qpart, *Amu, *Bmu, *dA, *dB, *T1, *lpart, *W2;
-  double* amax;  // [6] max |Phi|, |Psi|, |Abar|, |Bbar|, |g G|, |G| (binary16 split)
-  double* sc;    // [16] operand scales: Gram (4), dPhi (2), dPsi (2), padding (4), H (2), padding (2)
+  // binary16 split: operand maxima and power-of-two scales
+  //  amax [8]: block rows of Phi, Psi; interpolation rows (E) of Phi, Psi; Abar, Bbar; g G, G
+  //  sc [20]: Gram (rows Phi, E_phi, rows Psi, E_psi); Abar F (Abar, E_phi, Bbar, E_psi);
+  //           Abar^T X (Abar, rows Phi, Bbar, rows Psi); H (g G, G, -, -); Gram of the
+  //           interpolation rows (E_phi, E_phi, E_psi, E_psi)
+  double* amax;
+  double* sc;
   void* tp;      // transposed planes of the products over grid rows (H, Abar^T X), split precisions
   double* tpart; // split-K partials of those products (null: never split)
   SplitWork sw;  // orbital-row and Gram right-hand-side planes (split precisions)
@@ -408,8 +413,8 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   const int nmax = n_phi > n_psi ? n_phi : n_psi;
   P.st = c.take<FitState>(1);
   P.marker = c.take<int>(nr);
-  P.amax = c.take<double>(6);
-  P.sc = c.take<double>(16);
+  P.amax = c.take<double>(8);
+  P.sc = c.take<double>(20);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize);
   P.Fphi = c.take<char>((size_t)2 * n_phi * 2 * n_mu * tsize);
   P.Xphi = c.take<char>((size_t)n_mu * 2 * n_phi * tsize);
@@ -545,18 +550,19 @@ static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec
 template <int PREC, class TS>
 static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const void* fplanes,
                           const TS* X, int64_t ld_x, int n, TS* dX, int64_t ld_dx, int64_t r, int rows, double* Q,
-                          double* Qpart, const double* scales, const AdjPlanes& ap, int sp, bool first, void* tp,
-                          double* tpart, int slots, const int* ab, hipStream_t s) {
+                          double* Qpart, const double* scales, const double* scales_t, const AdjPlanes& ap, int sp,
+                          bool first, void* tp, double* tpart, int slots, const int* ab, hipStream_t s) {
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s))
     return false;
   constexpr int SPLIT = Prec<PREC>::SPLIT;
   if constexpr (SPLIT >= 0) {
-    // binary16 scales (s_Abar, s_X) = scales[0..1]
+    // binary16 scales (s_Abar, s_X) = scales_t[0..1]
     return split_xty<SPLIT, TS>(Abar, two_mu, (int)two_mu, nullptr, X + 2 * r * ld_x, 2 * ld_x, 2 * n, rows, Q,
-                                2 * (int64_t)n, !first, 0, tp, tpart, SPLIT == SPLIT_FP16X3 ? scales : nullptr, slots,
-                                ab, s);
+                                2 * (int64_t)n, !first, 0, tp, tpart, SPLIT == SPLIT_FP16X3 ? scales_t : nullptr,
+                                slots, ab, s);
   } else {
+    (void)scales_t;
     (void)tp;
     (void)tpart;
     (void)slots;
@@ -626,7 +632,14 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
                          ld_psi, n_psi, idx, n_mu, nr, Xpsi);
     }
     if (!launch_ok()) return ISDF_E_HIP;
-    if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
+    // binary16 scales of the interpolation rows (E, F, the rows' Gram at the
+    // end); the grid rows' scales follow block by block
+    if (!gram_scales_rows<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, 0, 0, (const double*)Ephi,
+                                    (const double*)Epsi, nmu16, P.amax, P.sc, s))
+      return ISDF_E_HIP;
+    if (Prec<PREC>::SPLIT == SPLIT_FP16X3)
+      hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 16, 2, 2,
+                         aliased ? 2 : 3, aliased ? 2 : 3);
     if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
       return ISDF_E_HIP;
     if constexpr (Prec<PREC>::SPLIT >= 0) {  // F planes, scaled like the orbitals (sc[1], sc[3])
@@ -652,6 +665,10 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
     double* Bb = aliased ? nullptr : (Bs ? Bs + (r - gbase) * 2 * n_mu : P.B);
     double* Abar = aliased ? Ab : Bb;  // after the Hadamard step
     double* Bbar = Ab;
+    // binary16 scales of this block's orbital rows (sc[0], sc[2])
+    if (!gram_scales_rows<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, r, rows, (const double*)Ephi,
+                                    (const double*)Epsi, nmu16, P.amax, P.sc, s))
+      return ISDF_E_HIP;
     if (!Gs && !gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr, nr,
                                r, rows, Gb, n1, aliased ? G_REAL : G_CPLX, ab, s, P.sc, &P.sw, Ab, Bb))
       return ISDF_E_HIP;
@@ -665,10 +682,10 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       if constexpr (SPLIT >= 0) {
         const double* hsc = nullptr;
         if (SPLIT == SPLIT_FP16X3) {  // binary16 scales of g G and G
-          if (!fill<double>(P.amax + 4, 2, 0.0, s)) return ISDF_E_HIP;
+          if (!fill<double>(P.amax + 6, 2, 0.0, s)) return ISDF_E_HIP;
           hipLaunchKernelGGL(absmax_real2, dim3((unsigned)(rows < 2048 ? rows : 2048)), dim3(256), 0, s,
-                             (const double*)Gb, (int64_t)n1, n1, (int64_t)rows, g + r, P.amax + 4);
-          hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 12, 4, 5, 4, 5);
+                             (const double*)Gb, (int64_t)n1, n1, (int64_t)rows, g + r, P.amax + 6);
+          hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 12, 6, 7, 6, 7);
           if (!launch_ok()) return ISDF_E_HIP;
           hsc = P.sc + 12;
         }
@@ -685,9 +702,9 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
       }
       // S = 2 g . (G (C C^H)^-2): Abar / Bbar in place, the loss and (binary16
       // split) the largest |Abar|, |Bbar| for their scales, in the epilogue
-      if (SPLIT == SPLIT_FP16X3 && !fill<double>(P.amax + 2, 2, 0.0, s)) return ISDF_E_HIP;
+      if (SPLIT == SPLIT_FP16X3 && !fill<double>(P.amax + 4, 2, 0.0, s)) return ISDF_E_HIP;
       EpiSAdj epi{Gb,  n1, Ab, Bb, 2 * (int64_t)n_mu, g + r, rows, n1, aliased ? 1 : 0, P.lpart,
-                  SPLIT == SPLIT_FP16X3 ? P.amax + 2 : nullptr};
+                  SPLIT == SPLIT_FP16X3 ? P.amax + 4 : nullptr};
       Operand<double> a{Gb, n1, nullptr, nullptr}, b{P.W2, n1, nullptr, nullptr};
       if (!launch_gemm<double, 128, 128, 16, 2, 2, double, KC, double, KC, 1>(rows, n1, n1, a, b, a, b, 0, epi, 0, ab,
                                                                              s))
@@ -714,19 +731,21 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
     }
     if (SPLIT == SPLIT_FP16X3) {  // binary16 scales of Abar, Phi, Bbar, Psi
       if (tbar) {  // (the fused loss found the maxima in its epilogue)
-        if (!fill<double>(P.amax + 2, 2, 0.0, s)) return ISDF_E_HIP;
-        if (!absmax<double>(Abar, n_mu, n_mu, rows, P.amax + 2, s)) return ISDF_E_HIP;
-        if (!aliased && !absmax<double>(Bbar, n_mu, n_mu, rows, P.amax + 3, s)) return ISDF_E_HIP;
+        if (!fill<double>(P.amax + 4, 2, 0.0, s)) return ISDF_E_HIP;
+        if (!absmax<double>(Abar, n_mu, n_mu, rows, P.amax + 4, s)) return ISDF_E_HIP;
+        if (!aliased && !absmax<double>(Bbar, n_mu, n_mu, rows, P.amax + 5, s)) return ISDF_E_HIP;
       }
-      hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 4, 2, 0, 3,
-                         aliased ? 0 : 1);
+      hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 4, 4, 2,
+                         aliased ? 4 : 5, aliased ? 2 : 3);
+      hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)P.amax, P.sc + 8, 4, 0,
+                         aliased ? 4 : 5, aliased ? 0 : 1);
     }
     if (!orbital_block<PREC, TS>(Abar, n_mu, Fphi, P.ap.f_phi, phi, ld_phi, n_phi, dphi, ld_dphi, r, rows, P.Qphi,
-                                 P.Qpart, P.sc + 4, P.ap, sp_phi.q, first, P.tp, P.tpart, P.slots, ab, s))
+                                 P.Qpart, P.sc + 4, P.sc + 8, P.ap, sp_phi.q, first, P.tp, P.tpart, P.slots, ab, s))
       return ISDF_E_HIP;
     if (!aliased && !orbital_block<PREC, TS>(Bbar, n_mu, Fpsi, P.ap.f_psi, psi, ld_psi, n_psi, dpsi, ld_dpsi, r, rows,
-                                             P.Qpsi, P.Qpart, P.sc + 6, P.ap, sp_psi.q, first, P.tp, P.tpart, P.slots,
-                                             ab, s))
+                                             P.Qpsi, P.Qpart, P.sc + 6, P.sc + 10, P.ap, sp_psi.q, first, P.tp,
+                                             P.tpart, P.slots, ab, s))
       return ISDF_E_HIP;
   }
   if (!(phases & BWD_END)) return ISDF_OK;
@@ -739,7 +758,7 @@ static int bwd_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const T
   }
   // Mbar terms at the interpolation rows
   if (!gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, idx, nr, 0, n_mu,
-                      nullptr, n1, G_CPLX, ab, s, P.sc, &P.sw, P.Amu, aliased ? nullptr : P.Bmu))
+                      nullptr, n1, G_CPLX, ab, s, P.sc + 16, &P.sw, P.Amu, aliased ? nullptr : P.Bmu))
     return ISDF_E_HIP;
   hipLaunchKernelGGL(mbar_hadamard, dim3(blocks_for((int64_t)n_mu * n_mu)), dim3(256), 0, s, (const double*)P.P,
                      (const double*)P.Amu, (const double*)P.Bmu, P.dA, P.dB, n_mu, aliased ? 1 : 0, ab);

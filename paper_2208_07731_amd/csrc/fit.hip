@@ -305,7 +305,7 @@ static ZcPlan plan_zc(void* ws, size_t cap, int n_mu, int n_phi, int n_psi, bool
   ZcPlan P{};
   const int nmu16 = (int)ceil_div(n_mu, 16) * 16;
   P.ab = c.take<int>(64);
-  P.amax = c.take<double>(2);
+  P.amax = c.take<double>(4);
   P.sc = c.take<double>(4);
   P.Ephi = c.take<char>((size_t)2 * nmu16 * 2 * n_phi * tsize_of(prec));
   P.Epsi = aliased ? P.Ephi : c.take<char>((size_t)2 * nmu16 * 2 * n_psi * tsize_of(prec));
@@ -333,7 +333,11 @@ static int zc_run(int64_t nr, const TS* phi, int64_t ld_phi, int n_phi, const TS
   if (!fill<int>(P.ab, 1, 0, s)) return ISDF_E_HIP;
   if (!pack<TS, T>(phi, ld_phi, n_phi, idx, n_mu, nr, nmu16, Ephi, s)) return ISDF_E_HIP;
   if (!aliased && !pack<TS, T>(psi, ld_psi, n_psi, idx, n_mu, nr, nmu16, Epsi, s)) return ISDF_E_HIP;
-  if (!gram_scales<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, nr, P.amax, P.sc, s)) return ISDF_E_HIP;
+  // binary16 scales from this call's rows and the interpolation rows only
+  // (a pass over the whole grid per block would cost as much as the block)
+  if (!gram_scales_rows<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, row0, nrows, (const double*)Ephi,
+                                  (const double*)Epsi, nmu16, P.amax, P.sc, s))
+    return ISDF_E_HIP;
   if (!split_rhs<PREC>((const double*)Ephi, (const double*)Epsi, n_phi, n_psi, aliased, P.sc, &P.sw, s))
     return ISDF_E_HIP;
   if (nrows > 0 && !gram<PREC, TS>(phi, ld_phi, n_phi, psi, ld_psi, n_psi, aliased, Ephi, Epsi, nmu16, n_mu, nullptr,

@@ -466,6 +466,28 @@ static bool gram_scales(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi,
   return launch_ok();
 }
 
+// Operand scales of a Gram product over the rows [r0, r0 + rows) only
+// (FP16 split; a power of two per operand, so any bound of its magnitude
+// will do): sc[0], sc[2] for those rows of Phi and Psi, sc[1], sc[3] for the
+// packed right-hand sides E_phi, E_psi (the interpolation rows), whose
+// maxima land in amax[2], amax[3]; amax[0], amax[1] receive the rows'.
+template <int PREC, class TS>
+static bool gram_scales_rows(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_t ld_psi, int n_psi,
+                             bool aliased, int64_t r0, int64_t rows, const double* Ephi, const double* Epsi,
+                             int nmu16, double* amax, double* sc, hipStream_t s) {
+  if (Prec<PREC>::SPLIT != SPLIT_FP16X3) return true;
+  if (!fill<double>(amax, 4, 0.0, s)) return false;
+  if (rows > 0 && !absmax<TS>(phi + 2 * r0 * ld_phi, ld_phi, n_phi, rows, amax, s)) return false;
+  if (!absmax<double>(Ephi, n_phi, n_phi, 2 * (int64_t)nmu16, amax + 2, s)) return false;
+  if (!aliased) {
+    if (rows > 0 && !absmax<TS>(psi + 2 * r0 * ld_psi, ld_psi, n_psi, rows, amax + 1, s)) return false;
+    if (!absmax<double>(Epsi, n_psi, n_psi, 2 * (int64_t)nmu16, amax + 3, s)) return false;
+  }
+  hipLaunchKernelGGL(pow2_scales, dim3(1), dim3(1), 0, s, (const double*)amax, sc, 0, 2, aliased ? 0 : 1,
+                     aliased ? 2 : 3);
+  return launch_ok();
+}
+
 // Gram + Hadamard of `rows` orbital rows (gathered through `gather` if
 // non-null, else starting at row r0) into G (and optionally A, B).
 template <int PREC, class TS>
