@@ -81,7 +81,9 @@ struct SplitCfg {
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int MI = WTM / 16, NI = WTN / 16;
   static constexpr int BK = 32;
-  static constexpr int LDK = BK + 8;  // LDS row of one part, 16-bit elements (80 bytes)
+  // LDS row of one part: 32 16-bit elements (64 bytes, unpadded); the four
+  // 16-byte chunks of a row are stored at chunk ^ swz(row), see lds_chunk
+  static constexpr int LDK = BK;
   static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile");
   __device__ __forceinline__ static int orow(int lane, int j) { return 4 * (lane >> 4) + j; }
 };
@@ -97,15 +99,26 @@ struct PlaneOp {
   const int* rows;  // optional gather of x, may be null
 };
 
-// Stages one 32-deep slice of a plane operand: the NP x X x 4 16-byte
-// chunks are spread over the workgroup and copied to LDS [NP][X][LDK].
-template <int MODE, int X, int THREADS>
+// LDS position of 16-byte chunk c (0..3) of staged row r.  LDS serves 32
+// lanes of a 16-byte access per cycle from 128 four-byte banks: a fragment
+// read (16 consecutive rows, chunks 2h and 2h + 1 for lane groups h) and a
+// staging store (8 consecutive rows from a multiple of 8, all four chunks)
+// then hit 32 distinct 16-byte slots when rows 8..15 of every 16 swap chunk
+// pairs (0,1) <-> (2,3).
+__device__ __forceinline__ int lds_chunk(int r, int c) { return c ^ ((r >> 2) & 2); }
+
+// Stages one stage of SUB 32-deep slices of a plane operand: the
+// NP x X x 4 16-byte chunks of a slice are spread over the workgroup (the
+// same chunks of every slice for one thread) and copied to LDS
+// [SUB][NP][X][LDK].
+template <int MODE, int X, int THREADS, int SUB>
 struct PlaneStager {
   typedef SplitT<MODE> S;
   typedef typename S::V V;
   static constexpr int CHUNKS = S::NP * X * 4;
   static constexpr int PER = (CHUNKS + THREADS - 1) / THREADS;
-  V v[PER];
+  static_assert(X % 16 == 0, "rows of a stage");
+  V v[SUB][PER];
   int64_t off[PER];  // element offset of each chunk's row start (without k)
   __device__ __forceinline__ void init(const PlaneOp<typename S::P>& op, int x0, int xlim, int tid) {
 #pragma unroll
@@ -118,21 +131,29 @@ struct PlaneStager {
       off[c] = q * op.pstride + row * op.ld + 8 * (rem % 4);
     }
   }
-  __device__ __forceinline__ void load(const PlaneOp<typename S::P>& op, int64_t k0, int tid) {
+  // slices k0, k0 + 32, ... of the first nsub of the stage
+  __device__ __forceinline__ void load(const PlaneOp<typename S::P>& op, int64_t k0, int nsub, int tid) {
 #pragma unroll
-    for (int c = 0; c < PER; ++c)
-      if (CHUNKS % THREADS == 0 || tid + c * THREADS < CHUNKS)
-        v[c] = *reinterpret_cast<const V*>(op.p + off[c] + k0);
+    for (int u = 0; u < SUB; ++u)
+      if (u == 0 || u < nsub)
+#pragma unroll
+        for (int c = 0; c < PER; ++c)
+          if (CHUNKS % THREADS == 0 || tid + c * THREADS < CHUNKS)
+            v[u][c] = *reinterpret_cast<const V*>(op.p + off[c] + k0 + 32 * u);
   }
-  __device__ __forceinline__ void store(typename S::P* s, int lds_k, int tid) const {
+  __device__ __forceinline__ void store(typename S::P* s, int lds_k, int nsub, int tid) const {
 #pragma unroll
-    for (int c = 0; c < PER; ++c) {
-      const int id = tid + c * THREADS;
-      if (CHUNKS % THREADS == 0 || id < CHUNKS) {
-        const int q = id / (X * 4), rem = id % (X * 4);
-        *reinterpret_cast<V*>(s + (q * X + rem / 4) * lds_k + 8 * (rem % 4)) = v[c];
-      }
-    }
+    for (int u = 0; u < SUB; ++u)
+      if (u == 0 || u < nsub)
+#pragma unroll
+        for (int c = 0; c < PER; ++c) {
+          const int id = tid + c * THREADS;
+          if (CHUNKS % THREADS == 0 || id < CHUNKS) {
+            const int q = id / (X * 4), rem = id % (X * 4);
+            const int r = q * X + rem / 4;
+            *reinterpret_cast<V*>(s + (u * S::NP * X + r) * lds_k + 8 * lds_chunk(r, rem % 4)) = v[u][c];
+          }
+        }
   }
 };
 
@@ -151,9 +172,18 @@ __device__ __forceinline__ void flush_acc(f4v (&acc)[Cfg::MI][Cfg::NI], d4v (&ac
     }
 }
 
+// Number of 32-deep slices per LDS stage: two where the registers allow a
+// second staged slice (two 16-bit parts), one otherwise.
+template <int MODE>
+struct SplitSub {
+  static constexpr int value = SplitT<MODE>::NP == 2 ? 2 : 1;
+};
+
 // K loop of one operand pair into the leading (acc0, folded into accd every
-// FLUSH slices) and correction (acc1) accumulators.  Single LDS buffer, the
-// next slice prefetched in registers.
+// FLUSH slices) and correction (acc1) accumulators.  Single LDS buffer of
+// SUB slices, the next stage prefetched in registers; the products and the
+// fold points are those of a loop over single slices, so SUB does not
+// change a bit of the result.
 template <int MODE, class Cfg, int BM, int BN, int FLUSH>
 __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::P>& A,
                                            const PlaneOp<typename SplitT<MODE>::P>& B, int m0, int n0, int M, int N,
@@ -164,56 +194,69 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
   typedef typename S::P P;
   typedef typename S::V V;
   constexpr int LDK = Cfg::LDK;
+  constexpr int SUB = SplitSub<MODE>::value;
+  constexpr int BK = Cfg::BK;
   P* As = smem;
-  P* Bs = smem + S::NP * BM * LDK;
+  P* Bs = smem + SUB * S::NP * BM * LDK;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv / (BN / Cfg::WTN), wn = wv % (BN / Cfg::WTN);
-  PlaneStager<MODE, BM, Cfg::THREADS> sa;
-  PlaneStager<MODE, BN, Cfg::THREADS> sb;
+  PlaneStager<MODE, BM, Cfg::THREADS, SUB> sa;
+  PlaneStager<MODE, BN, Cfg::THREADS, SUB> sb;
   sa.init(A, m0, M, tid);
   sb.init(B, n0, N, tid);
   if (K <= kbeg) return;
-  sa.load(A, kbeg, tid);
-  sb.load(B, kbeg, tid);
-  sa.store(As, LDK, tid);
-  sb.store(Bs, LDK, tid);
+  // K - kbeg is a multiple of BK: slices in a stage starting at k
+  auto nsub_at = [&](int64_t k) { return (int)((K - k) / BK < SUB ? (K - k) / BK : SUB); };
+  sa.load(A, kbeg, nsub_at(kbeg), tid);
+  sb.load(B, kbeg, nsub_at(kbeg), tid);
+  sa.store(As, LDK, nsub_at(kbeg), tid);
+  sb.store(Bs, LDK, nsub_at(kbeg), tid);
   __syncthreads();
-  const int q8 = 8 * (lane >> 4);
+  // fragment rows are 16-aligned plus lane & 15, so the swizzle depends on the lane only
+  const int q8 = 8 * lds_chunk(lane & 15, lane >> 4);
   int step = 0;
-  for (int64_t k0 = kbeg; k0 < K; k0 += Cfg::BK) {
-    const bool more = k0 + Cfg::BK < K;
+  for (int64_t k0 = kbeg; k0 < K; k0 += SUB * BK) {
+    const int64_t kn = k0 + SUB * BK;
+    const bool more = kn < K;
+    const int nn = more ? nsub_at(kn) : 0, nc = nsub_at(k0);
     if (more) {
-      sa.load(A, k0 + Cfg::BK, tid);
-      sb.load(B, k0 + Cfg::BK, tid);
-    }
-    V a[S::NP][Cfg::MI], b[S::NP][Cfg::NI];
-#pragma unroll
-    for (int p = 0; p < S::NP; ++p) {
-#pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i)
-        a[p][i] = *reinterpret_cast<const V*>(As + (p * BM + wm * Cfg::WTM + i * 16 + (lane & 15)) * LDK + q8);
-#pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j)
-        b[p][j] = *reinterpret_cast<const V*>(Bs + (p * BN + wn * Cfg::WTN + j * 16 + (lane & 15)) * LDK + q8);
+      sa.load(A, kn, nn, tid);
+      sb.load(B, kn, nn, tid);
     }
 #pragma unroll
-    for (int pp = 1; pp < S::NPROD; ++pp)
+    for (int u = 0; u < SUB; ++u) {
+      if (u > 0 && u >= nc) break;
+      const P* Au = As + u * S::NP * BM * LDK;
+      const P* Bu = Bs + u * S::NP * BN * LDK;
+      V a[S::NP][Cfg::MI], b[S::NP][Cfg::NI];
+#pragma unroll
+      for (int p = 0; p < S::NP; ++p) {
+#pragma unroll
+        for (int i = 0; i < Cfg::MI; ++i)
+          a[p][i] = *reinterpret_cast<const V*>(Au + (p * BM + wm * Cfg::WTM + i * 16 + (lane & 15)) * LDK + q8);
+#pragma unroll
+        for (int j = 0; j < Cfg::NI; ++j)
+          b[p][j] = *reinterpret_cast<const V*>(Bu + (p * BN + wn * Cfg::WTN + j * 16 + (lane & 15)) * LDK + q8);
+      }
+#pragma unroll
+      for (int pp = 1; pp < S::NPROD; ++pp)
+#pragma unroll
+        for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+          for (int j = 0; j < Cfg::NI; ++j) S::mma(a[S::pa(pp)][i], b[S::pb(pp)][j], acc1[i][j]);
 #pragma unroll
       for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
-        for (int j = 0; j < Cfg::NI; ++j) S::mma(a[S::pa(pp)][i], b[S::pb(pp)][j], acc1[i][j]);
-#pragma unroll
-    for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j) S::mma(a[0][i], b[0][j], acc0[i][j]);
-    if (++step == FLUSH) {
-      step = 0;
-      flush_acc<Cfg>(acc0, accd);
+        for (int j = 0; j < Cfg::NI; ++j) S::mma(a[0][i], b[0][j], acc0[i][j]);
+      if (++step == FLUSH) {
+        step = 0;
+        flush_acc<Cfg>(acc0, accd);
+      }
     }
     __syncthreads();
     if (more) {
-      sa.store(As, LDK, tid);
-      sb.store(Bs, LDK, tid);
+      sa.store(As, LDK, nn, tid);
+      sb.store(Bs, LDK, nn, tid);
       __syncthreads();
     }
   }
@@ -329,7 +372,7 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
   typedef SplitCfg<BM, BN, WM, WN> Cfg;
   typedef SplitT<MODE> S;
   if (sh.abort && *sh.abort) return;
-  __shared__ __attribute__((aligned(16))) typename S::P smem[S::NP * (BM + BN) * Cfg::LDK];
+  __shared__ __attribute__((aligned(16))) typename S::P smem[SplitSub<MODE>::value * S::NP * (BM + BN) * Cfg::LDK];
   const int tiles_n = (sh.N + BN - 1) / BN, tiles_m = (sh.M + BM - 1) / BM;
   const int ntiles = (int)split_tiles(tiles_m, tiles_n, BM / BN, sh.lower_only);
   // split-K: slice z of the K range per group of ntiles workgroups
