@@ -157,3 +157,46 @@ def test_water512_fused_loss_gradient_rows(c5):
     print(f"[water512] dphi rows rel err {err:.3e}")
     assert err <= FP64_GRAD
     assert info["status"] == 0 and np.isfinite(loss.item()) and loss.item() > 0
+
+
+def test_water512_step_as_benchmarked(c5):
+    """The 512-water step as the benchmark times it (ISDFStep with FP16x3
+    orbital contractions, blocks of 65536 rows, each block's Gram rows kept
+    for its share of the streamed adjoint): its interpolation points equal
+    those of a separate isdf_kmeans call, and Theta (rows of the last block,
+    the one the step keeps) and dPhi at sampled rows match the oracle on the
+    sub-problem of the step's interpolation rows plus the sampled rows, to
+    the mixed-precision bars."""
+    from paper_2208_07731_amd.pipeline import ISDFStep
+
+    d, wl = c5["d"], c5["wl"]
+    phi = d["phi"]
+    g = d["g"]
+    st = ISDFStep(phi, None, wl.n_mu, d["c0"], wl.kmeans_iters, g=torch.as_tensor(g, device="cuda"), prec="fp16x3",
+                  block_rows=BLOCK, keep_theta=False)
+    assert st.save_gram and len(st.blocks) == wl.n_r // BLOCK
+    print("[water512] benchmarked step on the GPU", flush=True)
+    st.enqueue()
+    info = st.check()
+    idx = st.idx.cpu().numpy()
+    km = isdf.kmeans(phi, None, wl.n_mu, d["c0"], wl.kmeans_iters, grid=wl.n)
+    assert np.array_equal(idx, km.idx.cpu().numpy())
+    last0 = wl.n_r - BLOCK
+    rng = np.random.default_rng(5007)
+    sample = np.sort(rng.choice(np.setdiff1d(np.arange(last0, wl.n_r), idx), 128, replace=False))
+    extra = np.sort(rng.choice(np.setdiff1d(np.arange(wl.n_r), np.concatenate([idx, sample])), 128, replace=False))
+    rows = np.concatenate([sample, extra])
+    got_t = st.theta[torch.as_tensor(sample - last0, device="cuda")].cpu().numpy()
+    got_g = st.dphi[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    sub = np.concatenate([idx, rows])
+    phi_sub = phi[torch.as_tensor(sub, device="cuda")].cpu().numpy()
+    del st
+    torch.cuda.empty_cache()
+    loc = np.arange(wl.n_mu)
+    print("[water512] oracle fit and adjoint on the step's sub-problem", flush=True)
+    ref_t = oracle.fit(phi_sub, phi_sub, loc)["theta"].real[wl.n_mu: wl.n_mu + sample.size]
+    ref_g = oracle.fit_backward(phi_sub, phi_sub, loc, g=g[sub])["dphi"][wl.n_mu:]
+    e_t, e_g = rel(got_t, ref_t), rel(got_g, ref_g)
+    print(f"[water512] step fp16x3: theta rows {e_t:.3e}, dphi rows {e_g:.3e}", flush=True)
+    assert e_t <= MIXED_THETA and e_g <= MIXED_GRAD
+    assert info["backward"]["status"] == 0 and info["fit"]["status"] == 0
