@@ -493,10 +493,14 @@ def main():
         return a.elapsed_time(b) / steps
 
     def run(prec, steps, warmup):
+        slow = wl.n_r > (1 << 20)  # steps of seconds: progress lines while the GPU works
         st = ISDFStep(phi, None if wl.aliased else psi, wl.n_mu, d["c0"], wl.kmeans_iters, g=g, prec=prec,
                       block_rows=block_rows, keep_theta=block_rows is None)
-        for _ in range(warmup):
+        for w in range(warmup):
             st.enqueue()
+            if slow:
+                torch.cuda.synchronize()
+                log(f"[bench] {prec}: warm-up step {w + 1} of {warmup} done")
         if warmup:
             st.check()
         ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
@@ -504,11 +508,18 @@ def main():
         blocks = [[(ev(), ev(), ev(), ev()) for _ in range(nb)] for _ in range(steps)]
         phases = [[ev() for _ in range(5)] for _ in range(steps)]
         factor = [(ev(), ev()) for _ in range(steps)]
+        done = [ev() for _ in range(steps)]
         torch.cuda.synchronize()
         start, stop = ev(), ev()
         start.record()
         for k in range(steps):
             st.enqueue(block_events=blocks[k], phase_events=phases[k], factor_events=factor[k])
+            done[k].record()
+            if slow and k > 0:
+                # one step stays queued while the host waits for the one before
+                # it, so the GPU never idles; this only paces the progress lines
+                done[k - 1].synchronize()
+                log(f"[bench] {prec}: timed step {k} of {steps} done")
         stop.record()
         torch.cuda.synchronize()
         info = st.check()

@@ -404,12 +404,16 @@ struct SplitWork {
   void* rows_b;      //                     of Psi    [NP][rows_cap][ldp_b]
   void* e_a;         // parts of the packed Gram right-hand side of Phi [NP][e_rows][ldp_a]
   void* e_b;         //                                          of Psi
-  int ldp_a, ldp_b;  // 2 n rounded up to 32
+  int ldp_a, ldp_b;  // row pitch of the planes
+  int k_a, k_b;      // K extent: 2 n rounded up to 32
   int64_t rows_cap;
   int e_rows;        // 2 N_mu rounded up to 32
 };
 
-static inline int ldp_of(int n) { return (int)ceil_div(2 * (int64_t)n, 32) * 32; }
+// K extent of the planes of an n-column complex operand (2 n reals rounded
+// up to 32) and their row pitch (the same; see ldk_of for a padded pitch).
+static inline int kext_of(int n) { return (int)ceil_div(2 * (int64_t)n, 32) * 32; }
+static inline int ldp_of(int n) { return kext_of(n); }
 static inline size_t plane_bytes(int np, int64_t rows, int ldp) { return (size_t)np * rows * ldp * 2; }
 
 template <int MODE, class TS>
@@ -513,13 +517,13 @@ static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_
     PlaneOp<P> pa0{(const P*)sw->rows_a, sw->ldp_a, sw->rows_cap * sw->ldp_a, nullptr};
     PlaneOp<P> pb0{(const P*)sw->e_a, sw->ldp_a, (int64_t)sw->e_rows * sw->ldp_a, nullptr};
     if (aliased)
-      return launch_split<SPLIT, 128, 64, 2, 2, 1>(rows, N, sw->ldp_a, pa0, pb0, pa0, pb0, 0, sc, epi, abort, s);
+      return launch_split<SPLIT, 128, 64, 2, 2, 1>(rows, N, sw->k_a, pa0, pb0, pa0, pb0, 0, sc, epi, abort, s);
     if (!split_rows<SPLIT, TS>(psi, ld_psi, n_psi, gather, nr, gather ? 0 : r0, rows, sw->rows_b, sw->ldp_b,
                                sw->rows_cap, sc ? sc + 2 : nullptr, s))
       return false;
     PlaneOp<P> pa1{(const P*)sw->rows_b, sw->ldp_b, sw->rows_cap * sw->ldp_b, nullptr};
     PlaneOp<P> pb1{(const P*)sw->e_b, sw->ldp_b, (int64_t)sw->e_rows * sw->ldp_b, nullptr};
-    return launch_split<SPLIT, 64, 64, 2, 2, 2>(rows, N, sw->ldp_a, pa0, pb0, pa1, pb1, sw->ldp_b, sc, epi, abort, s);
+    return launch_split<SPLIT, 64, 64, 2, 2, 2>(rows, N, sw->k_a, pa0, pb0, pa1, pb1, sw->k_b, sc, epi, abort, s);
   } else {
     // FP32: accumulators folded into FP64 every 2 steps (32-deep)
     constexpr int FOLD = sizeof(T) == 4 ? 2 : 0;
@@ -587,6 +591,8 @@ static SplitWork carve_split(Carver& c, isdf_prec prec, int n_phi, int n_psi, bo
   const int np = prec == ISDF_P_BF16X6 ? 3 : 2;
   w.ldp_a = ldp_of(n_phi);
   w.ldp_b = ldp_of(n_psi);
+  w.k_a = kext_of(n_phi);
+  w.k_b = kext_of(n_psi);
   w.rows_cap = rows_cap;
   w.e_rows = (int)ceil_div(2 * (int64_t)ceil_div(n_mu, 16) * 16, 32) * 32;
   w.rows_a = c.take<char>(plane_bytes(np, rows_cap, w.ldp_a));
