@@ -292,7 +292,7 @@ __global__ void copy_rows(TS* __restrict__ dst, int64_t ldd, const TS* __restric
 static inline int kext_rows(int64_t rows) { return (int)ceil_div(rows, 32) * 32; }
 static inline int ldk_of(int64_t rows) { return kext_rows(rows) + 64; }
 
-// Split factor of a split-engine product with `tiles` output tiles (128 x 64)
+// Split factor of a split-engine product with `tiles` output tiles of the split tile
 // contracted over K grid rows: 1, or enough K slices of at least 4096 rows
 // to give every workgroup slot a tile.
 static int split_k_for(int64_t tiles, int64_t K, int slots) {
@@ -454,10 +454,12 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
     const int np = prec == ISDF_P_BF16X6 ? 3 : 2;
     const int64_t cols = 2 * n1 > 2 * (int64_t)n_mu + 2 * nmax ? 2 * n1 : 2 * (int64_t)n_mu + 2 * nmax;
     P.tp = c.take<char>((size_t)np * cols * ldk_of(rblock) * 2);
-    // split-K partials: the largest split factor over the block sizes that occur
-    const int t1 = (int)ceil_div(n1, 128);
-    const int64_t th = split_tiles(t1, (int)ceil_div(n1, 64), 2, 1);
-    const int64_t tq = ceil_div(2 * (int64_t)n_mu, 128) * ceil_div(2 * (int64_t)nmax, 64);
+    // split-K partials: the largest split factor over the block sizes that
+    // occur, with the output tile split_xty launches for this precision
+    const int bm = SplitTile<SPLIT_FP16X3>::BM, bn = SplitTile<SPLIT_FP16X3>::BN;
+    static_assert(SplitTile<SPLIT_BF16X6>::BM == bm && SplitTile<SPLIT_BF16X6>::BN == bn, "one tile");
+    const int64_t th = split_tiles((int)ceil_div(n1, bm), (int)ceil_div(n1, bn), bm / bn, 1);
+    const int64_t tq = ceil_div(2 * (int64_t)n_mu, bm) * ceil_div(2 * (int64_t)nmax, bn);
     int64_t need = 0;
     for (int64_t rows : {rblock, nr - (ceil_div(nr, rblock) - 1) * rblock}) {
       const int sh2 = split_k_for(th, kext_rows(rows), slots), sq2 = split_k_for(tq, kext_rows(rows), slots);
@@ -507,16 +509,18 @@ static bool split_xty(const double* X, int64_t ldx, int mx, const double* rowsca
   if (!split_t<SPLIT>(X, ldx, mx, rows, rowscale, ta, ldk, sc, s)) return false;
   if (!split_t<SPLIT>(Y, ldy, ny, rows, nullptr, tb, ldk, sc ? sc + 1 : nullptr, s)) return false;
   PlaneOp<P> a{ta, ldk, (int64_t)mx * ldk, nullptr}, b{tb, ldk, (int64_t)ny * ldk, nullptr};
+  typedef SplitTile<SPLIT> T;
   const int kx = kext_rows(rows);
-  const int64_t tiles = split_tiles((int)ceil_div(mx, 128), (int)ceil_div(ny, 64), 2, lower_only && mx == ny);
+  const int64_t tiles =
+      split_tiles((int)ceil_div(mx, T::BM), (int)ceil_div(ny, T::BN), T::BM / T::BN, lower_only && mx == ny);
   const int sp = part ? split_k_for(tiles, kx, slots) : 1;
   const int64_t cn = (int64_t)mx * ldc;
   if (sp == 1) {
     EpiStore<double> epi{C, ldc, mx, ny, 1.0, accumulate ? 1.0 : 0.0, nullptr, 0, 0};
-    return launch_split<SPLIT, 128, 64, 2, 2, 1>(mx, ny, kx, a, b, a, b, 0, sc, epi, ab, s, lower_only);
+    return launch_split<SPLIT, T::BM, T::BN, T::WM, T::WN, 1>(mx, ny, kx, a, b, a, b, 0, sc, epi, ab, s, lower_only);
   }
   EpiStore<double> epi{part, ldc, mx, ny, 1.0, 0.0, nullptr, cn, 0};
-  if (!launch_split<SPLIT, 128, 64, 2, 2, 1>(mx, ny, kx, a, b, a, b, 0, sc, epi, ab, s, lower_only, sp))
+  if (!launch_split<SPLIT, T::BM, T::BN, T::WM, T::WN, 1>(mx, ny, kx, a, b, a, b, 0, sc, epi, ab, s, lower_only, sp))
     return false;
   hipLaunchKernelGGL(reduce_splits, dim3(blocks_for(cn)), dim3(256), 0, s, C, (const double*)part, cn, sp,
                      accumulate ? 1 : 0, ab);
@@ -542,7 +546,8 @@ static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec
     EpiStore<TS> epi{dX, 2 * ld_dx, rows, 2 * n, 1.0, 0.0, nullptr, 0, 0};
     PlaneOp<P> a{(const P*)ap.abar, ap.ldp, ap.rows_cap * ap.ldp, nullptr};
     PlaneOp<P> b{(const P*)fplanes, ap.ldp, 2 * (int64_t)n * ap.ldp, nullptr};
-    return launch_split<SPLIT, 128, 64, 2, 2, 1>(rows, 2 * n, ap.kx, a, b, a, b, 0, sc, epi, ab, s);
+    typedef SplitTile<SPLIT> T;
+    return launch_split<SPLIT, T::BM, T::BN, T::WM, T::WN, 1>(rows, 2 * n, ap.kx, a, b, a, b, 0, sc, epi, ab, s);
   } else {
     (void)fplanes;
     (void)ap;

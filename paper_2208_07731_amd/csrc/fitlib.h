@@ -373,7 +373,20 @@ struct Prec<ISDF_P_FP16X3> {
 };
 
 // Slices between FP64 folds of the leading accumulator.
-constexpr int SPLIT_FLUSH = 2;
+#ifndef ISDF_SPLIT_FLUSH
+#define ISDF_SPLIT_FLUSH 2
+#endif
+constexpr int SPLIT_FLUSH = ISDF_SPLIT_FLUSH;
+
+// Output tile of the one-operand-pair split products: 128 x 128 with eight
+// wavefronts of 64 x 32 (one workgroup per CU at two wavefronts per SIMD).
+// Against 128 x 64 tiles of four wavefronts each operand panel serves twice
+// the outputs, and the 512 threads stage a slice with half the registers
+// each; bitwise the same products.
+template <int MODE>
+struct SplitTile {
+  static constexpr int BM = 128, BN = 128, WM = 2, WN = 4;
+};
 
 // lower_only (M = N): only the tiles that reach the lower triangle, for
 // symmetric products whose upper triangle is mirrored afterwards.
@@ -517,7 +530,8 @@ static bool gram(const TS* phi, int64_t ld_phi, int n_phi, const TS* psi, int64_
     PlaneOp<P> pa0{(const P*)sw->rows_a, sw->ldp_a, sw->rows_cap * sw->ldp_a, nullptr};
     PlaneOp<P> pb0{(const P*)sw->e_a, sw->ldp_a, (int64_t)sw->e_rows * sw->ldp_a, nullptr};
     if (aliased)
-      return launch_split<SPLIT, 128, 64, 2, 2, 1>(rows, N, sw->k_a, pa0, pb0, pa0, pb0, 0, sc, epi, abort, s);
+      return launch_split<SPLIT, SplitTile<SPLIT>::BM, SplitTile<SPLIT>::BN, SplitTile<SPLIT>::WM,
+                          SplitTile<SPLIT>::WN, 1>(rows, N, sw->k_a, pa0, pb0, pa0, pb0, 0, sc, epi, abort, s);
     if (!split_rows<SPLIT, TS>(psi, ld_psi, n_psi, gather, nr, gather ? 0 : r0, rows, sw->rows_b, sw->ldp_b,
                                sw->rows_cap, sc ? sc + 2 : nullptr, s))
       return false;

@@ -174,7 +174,7 @@ __device__ __forceinline__ void flush_acc(f4v (&acc)[Cfg::MI][Cfg::NI], d4v (&ac
 
 // Number of 32-deep slices per LDS stage: two where the registers allow a
 // second staged slice (two 16-bit parts), one otherwise.
-template <int MODE>
+template <int MODE, int THREADS>
 struct SplitSub {
   static constexpr int value = SplitT<MODE>::NP == 2 ? 2 : 1;
 };
@@ -194,7 +194,7 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
   typedef typename S::P P;
   typedef typename S::V V;
   constexpr int LDK = Cfg::LDK;
-  constexpr int SUB = SplitSub<MODE>::value;
+  constexpr int SUB = SplitSub<MODE, Cfg::THREADS>::value;
   constexpr int BK = Cfg::BK;
   P* As = smem;
   P* Bs = smem + SUB * S::NP * BM * LDK;
@@ -365,14 +365,14 @@ __host__ __device__ __forceinline__ int64_t split_tiles(int tiles_m, int tiles_n
 // summing K slice [z kchunk, (z + 1) kchunk) and handing z to the epilogue.  scales: null (BF16X6) or
 // device [s_A0, s_B0, s_A1, s_B1] the planes were scaled by (FP16X3).
 template <int MODE, int BM, int BN, int WM, int WN, int NOPS, int FLUSH, class Epi>
-__global__ __launch_bounds__(WM* WN* ISDF_WAVE, 2) void gemm_split_kernel(
+__global__ __launch_bounds__(WM* WN* ISDF_WAVE, WM* WN >= 8 ? 1 : 2) void gemm_split_kernel(
     GemmShape sh, PlaneOp<typename SplitT<MODE>::P> A0, PlaneOp<typename SplitT<MODE>::P> B0,
     PlaneOp<typename SplitT<MODE>::P> A1, PlaneOp<typename SplitT<MODE>::P> B1, int64_t K1, const double* scales,
     Epi epi) {
   typedef SplitCfg<BM, BN, WM, WN> Cfg;
   typedef SplitT<MODE> S;
   if (sh.abort && *sh.abort) return;
-  __shared__ __attribute__((aligned(16))) typename S::P smem[SplitSub<MODE>::value * S::NP * (BM + BN) * Cfg::LDK];
+  __shared__ __attribute__((aligned(16))) typename S::P smem[SplitSub<MODE, Cfg::THREADS>::value * S::NP * (BM + BN) * Cfg::LDK];
   const int tiles_n = (sh.N + BN - 1) / BN, tiles_m = (sh.M + BM - 1) / BM;
   const int ntiles = (int)split_tiles(tiles_m, tiles_n, BM / BN, sh.lower_only);
   // split-K: slice z of the K range per group of ntiles workgroups
