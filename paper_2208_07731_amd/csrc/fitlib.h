@@ -373,10 +373,7 @@ struct Prec<ISDF_P_FP16X3> {
 };
 
 // Slices between FP64 folds of the leading accumulator.
-#ifndef ISDF_SPLIT_FLUSH
-#define ISDF_SPLIT_FLUSH 2
-#endif
-constexpr int SPLIT_FLUSH = ISDF_SPLIT_FLUSH;
+constexpr int SPLIT_FLUSH = 2;
 
 // Output tile of the one-operand-pair split products: 128 x 128 with eight
 // wavefronts of 64 x 32 (one workgroup per CU at two wavefronts per SIMD).
