@@ -179,11 +179,22 @@ struct SplitSub {
   static constexpr int value = SplitT<MODE>::NP == 2 ? 2 : 1;
 };
 
+// LDS buffers of stages: with two, the next stage is stored into the other
+// buffer while this one feeds the MFMAs and one barrier per stage suffices.
+// The eight-wavefront tiles run one workgroup per CU, so their LDS has room
+// for two (FP16x3 128 KB, BF16x6 96 KB); a barrier there stalls every wave
+// of the CU, not one workgroup of two.
+template <int MODE, int THREADS>
+struct SplitBufs {
+  static constexpr int value = THREADS >= 512 ? 2 : 1;
+};
+
 // K loop of one operand pair into the leading (acc0, folded into accd every
-// FLUSH slices) and correction (acc1) accumulators.  Single LDS buffer of
-// SUB slices, the next stage prefetched in registers; the products and the
-// fold points are those of a loop over single slices, so SUB does not
-// change a bit of the result.
+// FLUSH slices) and correction (acc1) accumulators.  LDS stages of SUB
+// slices (one or two buffers, SplitBufs), the next stage prefetched in
+// registers; the products and the fold points are those of a loop over
+// single slices, so neither SUB nor the buffering changes a bit of the
+// result.
 template <int MODE, class Cfg, int BM, int BN, int FLUSH>
 __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::P>& A,
                                            const PlaneOp<typename SplitT<MODE>::P>& B, int m0, int n0, int M, int N,
@@ -195,7 +206,9 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
   typedef typename S::V V;
   constexpr int LDK = Cfg::LDK;
   constexpr int SUB = SplitSub<MODE, Cfg::THREADS>::value;
+  constexpr int NBUF = SplitBufs<MODE, Cfg::THREADS>::value;
   constexpr int BK = Cfg::BK;
+  constexpr int STAGE = SUB * S::NP * (BM + BN) * LDK;
   P* As = smem;
   P* Bs = smem + SUB * S::NP * BM * LDK;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -253,11 +266,23 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
         flush_acc<Cfg>(acc0, accd);
       }
     }
-    __syncthreads();
-    if (more) {
-      sa.store(As, LDK, nn, tid);
-      sb.store(Bs, LDK, nn, tid);
+    if constexpr (NBUF == 2) {
+      // the other buffer's last reads ended before the previous barrier
+      P* An = (As == smem) ? smem + STAGE : smem;
+      if (more) {
+        sa.store(An, LDK, nn, tid);
+        sb.store(An + SUB * S::NP * BM * LDK, LDK, nn, tid);
+      }
       __syncthreads();
+      As = An;
+      Bs = An + SUB * S::NP * BM * LDK;
+    } else {
+      __syncthreads();
+      if (more) {
+        sa.store(As, LDK, nn, tid);
+        sb.store(Bs, LDK, nn, tid);
+        __syncthreads();
+      }
     }
   }
   flush_acc<Cfg>(acc0, accd);
@@ -372,7 +397,8 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, WM* WN >= 8 ? 1 : 2) void gemm_s
   typedef SplitCfg<BM, BN, WM, WN> Cfg;
   typedef SplitT<MODE> S;
   if (sh.abort && *sh.abort) return;
-  __shared__ __attribute__((aligned(16))) typename S::P smem[SplitSub<MODE, Cfg::THREADS>::value * S::NP * (BM + BN) * Cfg::LDK];
+  __shared__ __attribute__((aligned(16))) typename S::P smem[SplitBufs<MODE, Cfg::THREADS>::value * SplitSub<MODE, Cfg::THREADS>::value * S::NP * (BM + BN) *
+                                                              Cfg::LDK];
   const int tiles_n = (sh.N + BN - 1) / BN, tiles_m = (sh.M + BM - 1) / BM;
   const int ntiles = (int)split_tiles(tiles_m, tiles_n, BM / BN, sh.lower_only);
   // split-K: slice z of the K range per group of ntiles workgroups
