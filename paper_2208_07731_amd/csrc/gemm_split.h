@@ -251,16 +251,18 @@ __device__ __forceinline__ void split_loop(const PlaneOp<typename SplitT<MODE>::
         for (int j = 0; j < Cfg::NI; ++j)
           b[p][j] = *reinterpret_cast<const V*>(Bu + (p * BN + wn * Cfg::WTN + j * 16 + (lane & 15)) * LDK + q8);
       }
+      // leading products first: the fold below reads acc0 while the
+      // correction products still run on the matrix cores
+#pragma unroll
+      for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::NI; ++j) S::mma(a[0][i], b[0][j], acc0[i][j]);
 #pragma unroll
       for (int pp = 1; pp < S::NPROD; ++pp)
 #pragma unroll
         for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
           for (int j = 0; j < Cfg::NI; ++j) S::mma(a[S::pa(pp)][i], b[S::pb(pp)][j], acc1[i][j]);
-#pragma unroll
-      for (int i = 0; i < Cfg::MI; ++i)
-#pragma unroll
-        for (int j = 0; j < Cfg::NI; ++j) S::mma(a[0][i], b[0][j], acc0[i][j]);
       if (++step == FLUSH) {
         step = 0;
         flush_acc<Cfg>(acc0, accd);
