@@ -409,6 +409,30 @@ def test_fit_split_precision_complex_ragged(prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
+def test_split_precision_aliased_odd_slices(prec):
+    """Phi = Psi through the one-operand-pair split kernels with K extents of
+    an odd number of 32-deep slices, so the last LDS stage holds one slice:
+    the Gram (2 N_e = 80 -> 96), Abar Phi_mu (2 N_mu = 140 -> 160) and the
+    products over grid rows in r-blocks of 130, 130 and 40 rows (160 and 64).
+    Theta and the fused-loss gradient against the oracle."""
+    rng = np.random.default_rng(23)
+    nr, n_e, n_mu = 300, 40, 70
+    phi = rng.standard_normal((nr, n_e)) + 1j * rng.standard_normal((nr, n_e))
+    idx = np.sort(rng.choice(nr, n_mu, replace=False)).astype(np.int32)
+    g = rng.uniform(0.5, 1.5, nr)
+    pt, it = dev(phi), dev(idx)
+    theta, minv, _ = isdf.fit(pt, None, it, grid=(nr, 1, 1), prec=prec, rblock=130)
+    ref = oracle.fit(phi, phi, idx)
+    e_t = rel(theta.cpu().numpy(), ref["theta"].real)
+    dphi, _, loss, info = isdf.fit_backward(pt, None, it, minv, g=dev(g), grid=(nr, 1, 1), prec=prec, rblock=130)
+    rb = oracle.fit_backward(phi, phi, idx, g=g)
+    e_g = rel(dphi.cpu().numpy(), rb["dphi"])
+    print(f"{prec} aliased odd slices: theta {e_t:.3e}, dphi {e_g:.3e}")
+    assert e_t <= MIXED_THETA and e_g <= MIXED_GRAD
+    assert info["status"] == 0
+
+
+@pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
 def test_zc_split_precision(prec):
     """Z C^H rows from isdf_zc against the oracle's A . conj(B)."""
     import ctypes as C
