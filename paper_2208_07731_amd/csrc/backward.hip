@@ -82,9 +82,6 @@ __global__ void reduce_splits(double* __restrict__ out, const double* __restrict
 // In the complex case the partner lane (column 2 nu + 1 - c) supplies the
 // other half of S_{r nu}.
 struct EpiSAdj {
-  // no raised MFMA priority: with this epilogue's HBM traffic the product
-  // runs about 2 % faster without it
-  static constexpr bool kPrio = false;
   const double* G;
   int64_t ldg;
   double* A;
