@@ -418,8 +418,17 @@ __global__ __launch_bounds__(WM* WN* ISDF_WAVE, WM* WN >= 8 ? 1 : 2) void gemm_s
     while (tm + 1 < tiles_m && (int64_t)q * (tm + 1) * (tm + 2) / 2 <= logical) ++tm;
     tn = logical - q * tm * (tm + 1) / 2;
   } else {
-    tm = logical / tiles_n;
-    tn = logical % tiles_n;
+    // column by column within groups of 4 row blocks: the tiles one XCD
+    // holds at a time (about 32, consecutive logical tiles) then span 4 row
+    // and 8 column blocks rather than 1 row and 32 column blocks, so fewer
+    // operand slices go through its L2 per K step (Z C^H Gram 7 %, Abar^T Phi
+    // 5 % faster at 512-water blocks; 8 row blocks no better)
+    constexpr int GR = 4;
+    const int first = (logical / (GR * tiles_n)) * GR;
+    const int rows_in = tiles_m - first < GR ? tiles_m - first : GR;
+    const int local = logical % (GR * tiles_n);
+    tm = first + local % rows_in;
+    tn = local / rows_in;
   }
   const int m0 = tm * BM, n0 = tn * BN;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
