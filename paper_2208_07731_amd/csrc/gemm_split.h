@@ -339,14 +339,36 @@ __global__ __launch_bounds__(256) void split_planes_t(const TS* __restrict__ X, 
   const double sc = scale ? *scale : 1.0;
   const int k0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int kk = ty; kk < 64; kk += 4) {
-    const int k = k0 + kk, c = c0 + tx;
-    double v = 0.0;
-    if (k < rows && c < ncols) {
-      v = (double)X[(int64_t)k * ld + c];
-      if (rowscale) v *= rowscale[k];
+  // all 16 loads of a thread in flight before any LDS write: addresses
+  // clamped into the block (rows, ncols >= 1 whenever there is a block),
+  // elements outside it zeroed afterwards
+  if (rows > 0 && ncols > 0) {
+    const int c = c0 + tx, cc = c < ncols ? c : ncols - 1;
+    double v[16], f[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int k = k0 + ty + 4 * t, kc = k < rows ? k : rows - 1;
+      v[t] = (double)X[(int64_t)kc * ld + cc];
     }
-    tile[kk][tx] = v;
+    if (rowscale) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int k = k0 + ty + 4 * t;
+        f[t] = rowscale[k < rows ? k : rows - 1];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) f[t] = 1.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int k = k0 + ty + 4 * t;
+      // the product with 1.0 is exact, so rows without a scale keep their value
+      tile[ty + 4 * t][tx] = (k < rows && c < ncols) ? v[t] * f[t] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) tile[ty + 4 * t][tx] = 0.0;
   }
   __syncthreads();
   // 64 columns x 8 runs of 8 consecutive k, two per thread
