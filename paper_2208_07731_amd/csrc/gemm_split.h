@@ -339,9 +339,10 @@ __global__ __launch_bounds__(256) void split_planes_t(const TS* __restrict__ X, 
   const double sc = scale ? *scale : 1.0;
   const int k0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  // all 16 loads of a thread in flight before any LDS write: addresses
-  // clamped into the block (rows, ncols >= 1 whenever there is a block),
-  // elements outside it zeroed afterwards
+  // all 16 loads of a thread (and its row scales) in flight before any LDS
+  // write: indices past the last row or column are clamped to it, so every
+  // address is inside X, and those elements are zeroed afterwards; an empty
+  // X (no rows or columns) only zeroes the tile
   if (rows > 0 && ncols > 0) {
     const int c = c0 + tx, cc = c < ncols ? c : ncols - 1;
     double v[16], f[16];
