@@ -96,28 +96,57 @@ struct EpiSAdj {
   __device__ __forceinline__ void apply(const Acc (&acc)[Cfg::MI][Cfg::NI], const TileAt& at) const {
     __shared__ double red[Cfg::THREADS / ISDF_WAVE];
     double sl = 0.0, ma = 0.0, mb = 0.0;
+    if (aliased) {
+      // One 16 x 16 tile at a time, its loads (indices clamped into the
+      // block, so without branches) all issued before its stores: a store
+      // into A, written in place, would otherwise keep every later load of
+      // G or A from starting before it.  Arithmetic and the order of the
+      // loss sum are those of one element at a time.
 #pragma unroll
-    for (int i = 0; i < Cfg::MI; ++i)
+      for (int i = 0; i < Cfg::MI; ++i)
 #pragma unroll
-      for (int j = 0; j < Cfg::NI; ++j) {
-        const int n = at.n_wave + j * 16 + (at.lane & 15);
+        for (int j = 0; j < Cfg::NI; ++j) {
+          const int n = at.n_wave + j * 16 + (at.lane & 15);
+          const int nc = n < N ? n : N - 1;
+          double gm[4], gv[4];
+          double2 xv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
-          const bool ok = m < M && n < N;
-          const double gm = ok ? g[m] : 0.0;
-          const double v = (double)acc[i][j][r];
-          const double s = 2.0 * gm * v;
-          if (ok) sl += gm * v * G[(int64_t)m * ldg + n];
-          if (aliased) {
-            if (ok) {
-              double2* a = reinterpret_cast<double2*>(A + (int64_t)m * ldab + 2 * n);
-              const double2 av = *a;
-              const double2 o = make_double2(s * av.x, s * av.y);
-              *a = o;
+          for (int r = 0; r < 4; ++r) {
+            const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
+            const int mc = m < M ? m : M - 1;
+            gm[r] = g[mc];
+            gv[r] = G[(int64_t)mc * ldg + nc];
+            xv[r] = *reinterpret_cast<const double2*>(A + (int64_t)mc * ldab + 2 * nc);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
+            if (m < M && n < N) {
+              const double v = (double)acc[i][j][r];
+              const double s = 2.0 * gm[r] * v;
+              sl += gm[r] * v * gv[r];
+              const double2 o = make_double2(s * xv[r].x, s * xv[r].y);
+              *reinterpret_cast<double2*>(A + (int64_t)m * ldab + 2 * n) = o;
               ma = fmax(ma, fmax(fabs(o.x), fabs(o.y)));
             }
-          } else {
+          }
+          __builtin_amdgcn_sched_barrier(0);  // one tile's loads in flight at a time
+        }
+    } else {
+      // Psi != Phi: one element at a time (lane pairs exchange S)
+#pragma unroll
+      for (int i = 0; i < Cfg::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::NI; ++j) {
+          const int n = at.n_wave + j * 16 + (at.lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = at.m_wave + i * 16 + Cfg::orow(at.lane, r);
+            const bool ok = m < M && n < N;
+            const double gm = ok ? g[m] : 0.0;
+            const double v = (double)acc[i][j][r];
+            const double s = 2.0 * gm * v;
+            if (ok) sl += gm * v * G[(int64_t)m * ldg + n];
             const double so = __shfl_xor(s, 1, ISDF_WAVE);
             if (ok) {
               const int nu = n >> 1, c = n & 1;
@@ -138,7 +167,7 @@ struct EpiSAdj {
             }
           }
         }
-      }
+    }
     sl = wave_sum(sl);
     if (at.lane == 0) red[threadIdx.x >> 6] = sl;
     if (amax) {
