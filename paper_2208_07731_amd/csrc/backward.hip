@@ -318,13 +318,30 @@ __global__ void copy_rows(TS* __restrict__ dst, int64_t ldd, const TS* __restric
 static inline int kext_rows(int64_t rows) { return (int)ceil_div(rows, 32) * 32; }
 static inline int ldk_of(int64_t rows) { return kext_rows(rows) + 64; }
 
-// Split factor of a split-engine product with `tiles` output tiles of the split tile
-// contracted over K grid rows: 1, or enough K slices of at least 4096 rows
-// to give every workgroup slot a tile.
-static int split_k_for(int64_t tiles, int64_t K, int slots) {
-  int s = 1;
-  while (s < MAX_SPLITS && tiles * s < slots && ceil_div(K, 2 * s) >= 4096) s *= 2;
-  return s;
+// Split factor of a split-engine product with `tiles` 128 x 128 output tiles
+// of mn elements in total, contracted over K grid rows.  The engine holds one
+// workgroup per CU (slots / 2 of them, slots counting two FP64 tiles per CU),
+// so a launch takes ceil(tiles s / CUs) waves of workgroups: the factor is the
+// power of two, with K slices of at least 4096 rows, that minimises the
+// modelled time waves (K / s) t_row + s mn 16 B / bw (the partial sums'
+// write and read), a larger one taken only for a modelled gain above 2 %.
+// t_row is the measured time of one tile per K row (FP16x3 34 ns, BF16x6
+// 51 ns); e.g. the 136 lower tiles of a 2048 x 2048 H over 262144 rows run in
+// 9 waves of 16 slices instead of 3 waves of 4.
+static int split_k_for(int64_t tiles, int64_t K, int64_t mn, int slots, int mode) {
+  const int64_t cus = slots / 2 > 0 ? slots / 2 : 1;
+  const double t_row = mode == SPLIT_BF16X6 ? 51e-9 : 34e-9;
+  const double bw = 4e12;
+  int best = 1;
+  double best_t = (double)ceil_div(tiles, cus) * (double)K * t_row;
+  for (int s = 2; s <= MAX_SPLITS && ceil_div(K, s) >= 4096; s *= 2) {
+    const double t = (double)ceil_div(tiles * s, cus) * ((double)K / s) * t_row + s * (double)mn * 16.0 / bw;
+    if (t < 0.98 * best_t) {
+      best = s;
+      best_t = t;
+    }
+  }
+  return best;
 }
 
 static unsigned blocks_for(int64_t n) {
@@ -484,13 +501,20 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
     // occur, with the output tile split_xty launches for this precision
     const int bm = SplitTile<SPLIT_FP16X3>::BM, bn = SplitTile<SPLIT_FP16X3>::BN;
     static_assert(SplitTile<SPLIT_BF16X6>::BM == bm && SplitTile<SPLIT_BF16X6>::BN == bn, "one tile");
+    // (Abar^T X per orbital set: a set with fewer columns has fewer tiles and
+    // may take a larger factor, so both sets are sized)
+    const int mode = prec == ISDF_P_BF16X6 ? SPLIT_BF16X6 : SPLIT_FP16X3;
     const int64_t th = split_tiles((int)ceil_div(n1, bm), (int)ceil_div(n1, bn), bm / bn, 1);
-    const int64_t tq = ceil_div(2 * (int64_t)n_mu, bm) * ceil_div(2 * (int64_t)nmax, bn);
     int64_t need = 0;
     for (int64_t rows : {rblock, nr - (ceil_div(nr, rblock) - 1) * rblock}) {
-      const int sh2 = split_k_for(th, kext_rows(rows), slots), sq2 = split_k_for(tq, kext_rows(rows), slots);
+      const int sh2 = split_k_for(th, kext_rows(rows), n1 * n1, slots, mode);
       if (sh2 > 1 && sh2 * n1 * n1 > need) need = sh2 * n1 * n1;
-      if (sq2 > 1 && sq2 * 2 * (int64_t)n_mu * 2 * nmax > need) need = sq2 * 2 * (int64_t)n_mu * 2 * nmax;
+      for (int n : {n_phi, aliased ? n_phi : n_psi}) {
+        const int64_t mn = 2 * (int64_t)n_mu * 2 * n;
+        const int64_t tq = ceil_div(2 * (int64_t)n_mu, bm) * ceil_div(2 * (int64_t)n, bn);
+        const int sq2 = split_k_for(tq, kext_rows(rows), mn, slots, mode);
+        if (sq2 > 1 && sq2 * mn > need) need = sq2 * mn;
+      }
     }
     if (need > 0) P.tpart = c.take<double>((size_t)need);
   }
@@ -539,7 +563,7 @@ static bool split_xty(const double* X, int64_t ldx, int mx, const double* rowsca
   const int kx = kext_rows(rows);
   const int64_t tiles =
       split_tiles((int)ceil_div(mx, T::BM), (int)ceil_div(ny, T::BN), T::BM / T::BN, lower_only && mx == ny);
-  const int sp = part ? split_k_for(tiles, kx, slots) : 1;
+  const int sp = part ? split_k_for(tiles, kx, (int64_t)mx * ny, slots, SPLIT) : 1;
   const int64_t cn = (int64_t)mx * ldc;
   if (sp == 1) {
     EpiStore<double> epi{C, ldc, mx, ny, 1.0, accumulate ? 1.0 : 0.0, nullptr, 0, 0};
