@@ -522,22 +522,34 @@ static BwdPlan plan_bwd(void* ws, size_t cap, int64_t nr, int n_mu, int n_phi, i
   return P;
 }
 
-template <int SPLIT>
-static bool split_t(const double* x, int64_t ld, int ncols, int rows, const double* rowscale, void* out, int ldk,
-                    const double* scale, hipStream_t s) {
+// Transposed split of X (and, with out2, of X without its row scale in the
+// same pass).
+template <int SPLIT, class TS>
+static bool split_t(const TS* x, int64_t ld, int ncols, int rows, const double* rowscale, void* out, int ldk,
+                    const double* scale, hipStream_t s, void* out2 = nullptr, const double* scale2 = nullptr) {
   typedef typename SplitT<SPLIT>::P P;
   dim3 grid((unsigned)ceil_div(ldk, 64), (unsigned)ceil_div(ncols, 64));
-  hipLaunchKernelGGL((split_planes_t<SPLIT, double>), grid, dim3(256), 0, s, x, ld, ncols, rows, rowscale, (P*)out,
-                     ldk, (int64_t)ncols * ldk, scale);
+  const int64_t ps = (int64_t)ncols * ldk;
+  if (out2)
+    hipLaunchKernelGGL((split_planes_t<SPLIT, TS, T_DUAL>), grid, dim3(256), 0, s, x, ld, ncols, rows, rowscale,
+                       (P*)out, ldk, ps, scale, (P*)out2, ldk, ps, scale2);
+  else
+    hipLaunchKernelGGL((split_planes_t<SPLIT, TS, T_ONE>), grid, dim3(256), 0, s, x, ld, ncols, rows, rowscale,
+                       (P*)out, ldk, ps, scale, (P*)nullptr, 0, (int64_t)0, (const double*)nullptr);
   return launch_ok();
 }
+
+// Transposed planes of X (out, as split_t) and its row planes (rout [NP]
+// [rows_cap][ldp], as split_rows) from one read of X.
 template <int SPLIT>
-static bool split_t(const float* x, int64_t ld, int ncols, int rows, const double* rowscale, void* out, int ldk,
-                    const double* scale, hipStream_t s) {
+static bool split_t_rows(const double* x, int64_t ld, int ncols, int rows, void* out, int ldk, const double* scale,
+                         void* rout, int ldp, int64_t rows_cap, const double* rscale, hipStream_t s) {
   typedef typename SplitT<SPLIT>::P P;
+  if (ldp % 8 != 0 || ldp > ceil_div(ncols, 64) * 64 || rows > rows_cap) return false;
   dim3 grid((unsigned)ceil_div(ldk, 64), (unsigned)ceil_div(ncols, 64));
-  hipLaunchKernelGGL((split_planes_t<SPLIT, float>), grid, dim3(256), 0, s, x, ld, ncols, rows, rowscale, (P*)out,
-                     ldk, (int64_t)ncols * ldk, scale);
+  hipLaunchKernelGGL((split_planes_t<SPLIT, double, T_ROWS>), grid, dim3(256), 0, s, x, ld, ncols, rows,
+                     (const double*)nullptr, (P*)out, ldk, (int64_t)ncols * ldk, scale, (P*)rout, ldp,
+                     rows_cap * ldp, rscale);
   return launch_ok();
 }
 
@@ -550,14 +562,21 @@ static bool split_t(const float* x, int64_t ld, int ncols, int rows, const doubl
 template <int SPLIT, class TY>
 static bool split_xty(const double* X, int64_t ldx, int mx, const double* rowscale, const TY* Y, int64_t ldy, int ny,
                       int rows, double* C, int64_t ldc, bool accumulate, int lower_only, void* tp, double* part,
-                      const double* sc, int slots, const int* ab, hipStream_t s) {
+                      const double* sc, int slots, const int* ab, hipStream_t s, bool x_split = false) {
   typedef typename SplitT<SPLIT>::P P;
   constexpr int NP = SplitT<SPLIT>::NP;
   const int ldk = ldk_of(rows);
   P* ta = (P*)tp;
   P* tb = ta + (int64_t)NP * mx * ldk;
-  if (!split_t<SPLIT>(X, ldx, mx, rows, rowscale, ta, ldk, sc, s)) return false;
-  if (!split_t<SPLIT>(Y, ldy, ny, rows, nullptr, tb, ldk, sc ? sc + 1 : nullptr, s)) return false;
+  if (x_split) {  // X's planes are in tp already (split_t_rows)
+    if (!split_t<SPLIT>(Y, ldy, ny, rows, nullptr, tb, ldk, sc ? sc + 1 : nullptr, s)) return false;
+  } else if ((const void*)X == (const void*)Y && sizeof(TY) == sizeof(double) && ldx == ldy && mx == ny) {
+    // X^T diag(g) X: both operands' planes from one read of X
+    if (!split_t<SPLIT>(X, ldx, mx, rows, rowscale, ta, ldk, sc, s, tb, sc ? sc + 1 : nullptr)) return false;
+  } else {
+    if (!split_t<SPLIT>(X, ldx, mx, rows, rowscale, ta, ldk, sc, s)) return false;
+    if (!split_t<SPLIT>(Y, ldy, ny, rows, nullptr, tb, ldk, sc ? sc + 1 : nullptr, s)) return false;
+  }
   PlaneOp<P> a{ta, ldk, (int64_t)mx * ldk, nullptr}, b{tb, ldk, (int64_t)ny * ldk, nullptr};
   typedef SplitTile<SPLIT> T;
   const int kx = kext_rows(rows);
@@ -584,14 +603,15 @@ static bool split_xty(const double* X, int64_t ldx, int mx, const double* rowsca
 template <int PREC, class TS>
 static bool adj_rows(int rows, const double* Abar, int n_mu, const typename Prec<PREC>::E* F, const void* fplanes,
                      int n, TS* dX, int64_t ld_dx, const double* scales, const AdjPlanes& ap, const int* ab,
-                     hipStream_t s) {
+                     hipStream_t s, bool abar_split = false) {
   typedef typename Prec<PREC>::E T;
   constexpr int SPLIT = Prec<PREC>::SPLIT;
   const int64_t two_mu = 2 * (int64_t)n_mu;
   if constexpr (SPLIT >= 0) {
     typedef typename SplitT<SPLIT>::P P;
     const double* sc = SPLIT == SPLIT_FP16X3 ? scales : nullptr;
-    if (!split_rows<SPLIT, double>(Abar, n_mu, n_mu, nullptr, rows, 0, rows, ap.abar, ap.ldp, ap.rows_cap, sc, s))
+    if (!abar_split &&
+        !split_rows<SPLIT, double>(Abar, n_mu, n_mu, nullptr, rows, 0, rows, ap.abar, ap.ldp, ap.rows_cap, sc, s))
       return false;
     EpiStore<TS> epi{dX, 2 * ld_dx, rows, 2 * n, 1.0, 0.0, nullptr, 0, 0};
     PlaneOp<P> a{(const P*)ap.abar, ap.ldp, ap.rows_cap * ap.ldp, nullptr};
@@ -614,15 +634,22 @@ static bool orbital_block(const double* Abar, int n_mu, const typename Prec<PREC
                           double* Qpart, const double* scales, const double* scales_t, const AdjPlanes& ap, int sp,
                           bool first, void* tp, double* tpart, int slots, const int* ab, hipStream_t s) {
   const int64_t two_mu = 2 * (int64_t)n_mu;
-  if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s))
-    return false;
   constexpr int SPLIT = Prec<PREC>::SPLIT;
   if constexpr (SPLIT >= 0) {
-    // binary16 scales (s_Abar, s_X) = scales_t[0..1]
+    // Abar's transposed planes (Abar^T X) and row planes (Abar F) from one
+    // read of Abar; binary16 scales (s_Abar, s_X) = scales_t[0..1], (s_Abar,
+    // s_F) = scales[0..1]
+    const bool h = SPLIT == SPLIT_FP16X3;
+    if (!split_t_rows<SPLIT>(Abar, two_mu, (int)two_mu, rows, tp, ldk_of(rows), h ? scales_t : nullptr, ap.abar,
+                             ap.ldp, ap.rows_cap, h ? scales : nullptr, s))
+      return false;
+    if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s, true))
+      return false;
     return split_xty<SPLIT, TS>(Abar, two_mu, (int)two_mu, nullptr, X + 2 * r * ld_x, 2 * ld_x, 2 * n, rows, Q,
-                                2 * (int64_t)n, !first, 0, tp, tpart, SPLIT == SPLIT_FP16X3 ? scales_t : nullptr,
-                                slots, ab, s);
+                                2 * (int64_t)n, !first, 0, tp, tpart, h ? scales_t : nullptr, slots, ab, s, true);
   } else {
+    if (!adj_rows<PREC, TS>(rows, Abar, n_mu, F, fplanes, n, dX + 2 * r * ld_dx, ld_dx, scales, ap, ab, s))
+      return false;
     (void)scales_t;
     (void)tp;
     (void)tpart;

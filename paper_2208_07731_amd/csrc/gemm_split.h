@@ -328,15 +328,27 @@ __global__ void split_planes(const TS* __restrict__ x, int64_t ld, int n, const 
 // given), k < rows, and zero for rows <= k < ldk: the grid rows become the
 // contiguous K index of a product contracted over them (X^T Y).  One tile
 // of 64 rows x 64 columns per workgroup, transposed through LDS; scale as in
-// split_planes.
-template <int MODE, class TS>
+// split_planes.  The same pass can write a second set of planes into out2
+// (row pitch ld2, plane stride pstride2, binary16 scale scale2):
+//   SECOND = T_DUAL: the transposed planes of X without the row scale, for
+//     X^T diag(g) X from one read of X;
+//   SECOND = T_ROWS: the row planes of X as split_planes writes them (columns
+//     ncols .. ld2-1 zero, rows < `rows`), for a product over X's columns
+//     (X F) and one over its rows (X^T Y) from one read of X.
+enum { T_ONE = 0, T_DUAL = 1, T_ROWS = 2 };
+template <int MODE, class TS, int SECOND>
 __global__ __launch_bounds__(256) void split_planes_t(const TS* __restrict__ X, int64_t ld, int ncols, int rows,
                                                       const double* __restrict__ rowscale,
                                                       typename SplitT<MODE>::P* __restrict__ out, int ldk,
-                                                      int64_t pstride, const double* scale) {
+                                                      int64_t pstride, const double* scale,
+                                                      typename SplitT<MODE>::P* __restrict__ out2, int ld2,
+                                                      int64_t pstride2, const double* scale2) {
   typedef SplitT<MODE> S;
+  constexpr bool DUAL = SECOND == T_DUAL;
   __shared__ double tile[64][65];
+  __shared__ double fk[64];  // DUAL: row scales of the tile (0 past the last row)
   const double sc = scale ? *scale : 1.0;
+  const double sc2 = (SECOND != T_ONE && scale2) ? *scale2 : 1.0;
   const int k0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   // all 16 loads of a thread (and its row scales) in flight before any LDS
@@ -364,12 +376,22 @@ __global__ __launch_bounds__(256) void split_planes_t(const TS* __restrict__ X, 
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       const int k = k0 + ty + 4 * t;
-      // the product with 1.0 is exact, so rows without a scale keep their value
-      tile[ty + 4 * t][tx] = (k < rows && c < ncols) ? v[t] * f[t] : 0.0;
+      // the product with 1.0 is exact, so rows without a scale keep their
+      // value; DUAL keeps X in the tile and applies the row scale when the
+      // scaled planes are written (the same product)
+      if (DUAL) {
+        tile[ty + 4 * t][tx] = (k < rows && c < ncols) ? v[t] : 0.0;
+        if (tx == 0) fk[ty + 4 * t] = k < rows ? f[t] : 0.0;
+      } else {
+        tile[ty + 4 * t][tx] = (k < rows && c < ncols) ? v[t] * f[t] : 0.0;
+      }
     }
   } else {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) tile[ty + 4 * t][tx] = 0.0;
+    for (int t = 0; t < 16; ++t) {
+      tile[ty + 4 * t][tx] = 0.0;
+      if (DUAL && tx == 0) fk[ty + 4 * t] = 0.0;
+    }
   }
   __syncthreads();
   // 64 columns x 8 runs of 8 consecutive k, two per thread
@@ -381,13 +403,56 @@ __global__ __launch_bounds__(256) void split_planes_t(const TS* __restrict__ X, 
 #pragma unroll
     for (int e8 = 0; e8 < 8; ++e8) {
       typename S::P o[S::NP];
-      S::split(tile[8 * run + e8][cc], sc, o);
+      const double x = tile[8 * run + e8][cc];
+      if (DUAL) {
+        // the row-scaled value rounded on its own, as the single-output pass
+        // stores it (no contraction of the product into the split's
+        // subtractions)
+#pragma clang fp contract(off)
+        S::split(x * fk[8 * run + e8], sc, o);
+      } else {
+        S::split(x, sc, o);
+      }
 #pragma unroll
       for (int p = 0; p < S::NP; ++p) w[p][e8] = o[p];
     }
 #pragma unroll
     for (int p = 0; p < S::NP; ++p)
       *reinterpret_cast<typename S::V*>(out + p * pstride + (int64_t)c * ldk + kb) = w[p];
+    if (DUAL) {
+#pragma unroll
+      for (int e8 = 0; e8 < 8; ++e8) {
+        typename S::P o[S::NP];
+        S::split(tile[8 * run + e8][cc], sc2, o);
+#pragma unroll
+        for (int p = 0; p < S::NP; ++p) w[p][e8] = o[p];
+      }
+#pragma unroll
+      for (int p = 0; p < S::NP; ++p)
+        *reinterpret_cast<typename S::V*>(out2 + p * pstride2 + (int64_t)c * ld2 + kb) = w[p];
+    }
+  }
+  if (SECOND == T_ROWS) {
+    // 64 rows x 8 runs of 8 consecutive columns, two per thread; ld2 is a
+    // multiple of 8 no larger than the column tiles' extent, so a run that
+    // starts inside a row ends inside it, and its columns past ncols are the
+    // tile's zeros
+    for (int q = threadIdx.x; q < 512; q += 256) {
+      const int kk = q >> 3, run = q & 7;
+      const int k = k0 + kk, cb = c0 + 8 * run;
+      if (k >= rows || cb >= ld2) continue;
+      typename S::V w[S::NP];
+#pragma unroll
+      for (int e8 = 0; e8 < 8; ++e8) {
+        typename S::P o[S::NP];
+        S::split(tile[kk][8 * run + e8], sc2, o);
+#pragma unroll
+        for (int p = 0; p < S::NP; ++p) w[p][e8] = o[p];
+      }
+#pragma unroll
+      for (int p = 0; p < S::NP; ++p)
+        *reinterpret_cast<typename S::V*>(out2 + p * pstride2 + (int64_t)k * ld2 + cb) = w[p];
+    }
   }
 }
 
