@@ -557,8 +557,9 @@ static bool split_t_rows(const double* x, int64_t ld, int ncols, int rows, void*
 // blocks X [rows][mx] and Y [rows][ny], on 16-bit matrix cores: both split
 // transposed into `tp` (X scaled by rowscale when given; binary16 operand
 // scales sc[0], sc[1]), then one split product, split over K into partial
-// slices (fixed-order reduction) when its tiles alone would not fill the
-// GPU.  lower_only (X = Y up to rowscale, mx = ny): the lower tiles only.
+// slices (fixed-order reduction) when split_k_for finds whole waves of
+// workgroups better filled that way.  lower_only (X = Y up to rowscale,
+// mx = ny): the lower tiles only.  x_split: X's planes are in tp already.
 template <int SPLIT, class TY>
 static bool split_xty(const double* X, int64_t ldx, int mx, const double* rowscale, const TY* Y, int64_t ldy, int ny,
                       int rows, double* C, int64_t ldc, bool accumulate, int lower_only, void* tp, double* part,
